@@ -1,0 +1,180 @@
+/*
+ * geoloc.h -- C ABI of the MI355X (gfx950) position-domain correlation library.
+ *
+ * Direct geolocation (Sec. III, Algorithm 1) searches a grid of candidate ground
+ * points. For every point p, every snapshot (here: step k of L samples of one
+ * contiguous capture) and every receiver pair (i, j), the expected TDOA and FDOA
+ * follow from the receivers' known positions and velocities (Sec. II-B,
+ * Eq. (3)-(10)); receiver j's samples are delay-shifted and the product with
+ * receiver i is Doppler-rotated and summed (Eq. (11)); the per-step grids are
+ * accumulated non-coherently and the peak is the emitter estimate.
+ *
+ *   J(p) = sum_pairs sum_k |C_k(p)|^2          (POWER, default)  or  sum |C_k(p)|  (MAG)
+ *   C_k(p) = sum_{n=kL}^{kL+L-1} y_i[n] conj(yt_j[n]) exp(+j 2 pi nu_k(p) t_n)
+ *   t_n = (n - kL - (L-1)/2) / f_s                       (time measured from the step centre)
+ *   D_k(p) = (tau_j - tau_i) f_s, nu_k(p) = f_j - f_i    (Eq. (7)-(9), delay in samples)
+ *   LINEAR: yt_j[n] = (1-a) y_j[n+d0] + a y_j[n+d0+1], d0 = floor(D), a = D - d0
+ *   ROUND : yt_j[n] = y_j[n + round(D)]  (Eq. (9); halves round away from zero)
+ *   y_j[m] = 0 for m outside [0, N).
+ *
+ * Conventions
+ *   - Every call returns a status (GEOLOC_OK or a negative code); nothing throws or
+ *     aborts across this boundary. Out-parameters are untouched on error, and
+ *     geoloc_last_error() returns a thread-local detail string.
+ *   - The caller owns every input and output buffer. A plan owns its device scratch
+ *     until geoloc_destroy(). geoloc_map() and geoloc_geometry() are asynchronous on
+ *     the caller's stream; geoloc_argmax() synchronises that stream.
+ *   - A plan must not be used from two threads at once; different plans are
+ *     independent.
+ *   - Flat point index = row * n_cols + col, rows = latitude (RECT grids); the
+ *     position in the lat/lon arrays for POINTS grids.
+ *   - Units: SI; angles are geocentric latitude / longitude in radians on a sphere.
+ *   - Requires a gfx950 device; anything else returns GEOLOC_EDEVICE.
+ */
+#ifndef GEOLOC_H
+#define GEOLOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEOLOC_ABI_VERSION 1
+
+/* status codes */
+#define GEOLOC_OK            0
+#define GEOLOC_EINVAL       -1   /* invalid argument or descriptor */
+#define GEOLOC_ENOMEM       -2   /* device or host allocation failed */
+#define GEOLOC_EDEVICE      -3   /* no usable gfx950 device */
+#define GEOLOC_ESTATE       -4   /* call out of order (e.g. plan already destroyed) */
+#define GEOLOC_ENAN         -5   /* NaN found in a map by geoloc_argmax */
+#define GEOLOC_EUNSUPPORTED -6   /* valid request this build does not implement */
+#define GEOLOC_ELAUNCH      -7   /* a HIP runtime call or kernel launch failed */
+
+/* method */
+#define GEOLOC_DIRECT_FP32   0   /* Eq. (11) evaluated per point in FP32 (FP64 geometry)  */
+#define GEOLOC_CAF_BF16      1   /* CAF table on MFMA, BF16 inputs, FP32 accumulate        */
+#define GEOLOC_CAF_FP16      2   /* CAF table on MFMA, FP16 inputs, FP32 accumulate        */
+
+/* delay_mode */
+#define GEOLOC_DELAY_LINEAR  0   /* two-tap linear fractional delay (default)              */
+#define GEOLOC_DELAY_ROUND   1   /* integer delay round(D), the paper's Eq. (9)            */
+
+/* accum_mode */
+#define GEOLOC_ACC_POWER     0   /* J = sum |C|^2 */
+#define GEOLOC_ACC_MAG       1   /* J = sum |C|   */
+
+/* grid_kind */
+#define GEOLOC_GRID_RECT     0   /* lat[n_rows] x lon[n_cols] */
+#define GEOLOC_GRID_POINTS   1   /* lat[P], lon[P], P = n_rows * n_cols */
+
+/* geoloc_map flags */
+#define GEOLOC_ACCUMULATE    1u  /* add into J_dev instead of overwriting it */
+
+typedef struct geoloc_plan_s* geoloc_plan_t;
+
+/* Plan descriptor. Pointers are host pointers read only during geoloc_plan(). */
+typedef struct geoloc_desc {
+    int32_t n_rx;              /* receivers in the captures (>= 2)                        */
+    int32_t n_pairs;           /* pairs summed into J; 0 -> all i < j                     */
+    const int32_t* pairs;      /* [n_pairs][2] = (reference i, shifted j); NULL if n_pairs == 0 */
+    int64_t n_samples;         /* N, samples per receiver                                 */
+    int64_t step_len;          /* L; N must be a multiple of L (K = N / L steps)          */
+    double fs_hz;              /* sample rate f_s (> 0)                                   */
+    double fc_hz;              /* carrier f_c (> 0); lambda = c / f_c, c = 299792458 m/s  */
+    int32_t grid_kind;         /* GEOLOC_GRID_RECT or GEOLOC_GRID_POINTS                  */
+    int32_t _pad0;
+    int64_t n_rows, n_cols;    /* grid shape; P = n_rows * n_cols (> 0)                   */
+    const double* lat;         /* RECT: [n_rows]; POINTS: [P]  (radians)                  */
+    const double* lon;         /* RECT: [n_cols]; POINTS: [P]  (radians)                  */
+    double earth_radius_m;     /* sphere radius (e.g. 6371000)                            */
+    double alt_m;              /* altitude of every candidate point above the sphere      */
+    int32_t method;            /* GEOLOC_DIRECT_FP32 / GEOLOC_CAF_BF16 / GEOLOC_CAF_FP16  */
+    int32_t delay_mode;        /* GEOLOC_DELAY_LINEAR / GEOLOC_DELAY_ROUND                */
+    int32_t accum_mode;        /* GEOLOC_ACC_POWER / GEOLOC_ACC_MAG                       */
+    int32_t caf_lags;          /* CAF: integer lags per table; 0 -> fit to the footprint  */
+    int32_t caf_bins;          /* CAF: Doppler bins per table; 0 -> 256                   */
+    int32_t caf_lag_lo_set;    /* CAF: nonzero -> use caf_lag_lo instead of fitting it    */
+    int32_t caf_lag_lo;        /* CAF: first lag of the table (samples)                   */
+    int32_t _pad1;
+    double caf_nu_lo_hz;       /* CAF: first bin centre; NaN -> fit to the footprint      */
+    double caf_nu_hi_hz;       /* CAF: last bin centre;  NaN -> fit to the footprint      */
+} geoloc_desc;
+
+/* Per-map inputs. */
+typedef struct geoloc_inputs {
+    const void* captures;      /* DEVICE pointer: complex64 interleaved (re, im float32),
+                                  [n_rx][n_samples], 8-byte aligned; read-only           */
+    const double* rx_state;    /* HOST pointer: [K][n_rx][6] ECEF position (m), velocity
+                                  (m/s) of each receiver at each step's centre instant   */
+    void* stream;              /* hipStream_t to run on; NULL = the null stream          */
+} geoloc_inputs;
+
+/* Plan facts, and kernel times accumulated since the last geoloc_set_timing();
+ * filled by geoloc_info(), which waits for the timed kernels to finish. */
+typedef struct geoloc_plan_info {
+    int64_t n_points, n_steps, n_pairs, n_samples, step_len;
+    int32_t method, delay_mode;
+    int32_t caf_lag_lo, caf_lags, caf_bins, _pad;
+    double caf_nu_lo_hz, caf_nu_hi_hz;
+    int64_t device_bytes;      /* device scratch owned by the plan                       */
+    int64_t timed_maps;        /* maps run with timing enabled                           */
+    int64_t correlate_launches;/* launches of the dominant correlation kernel            */
+    double geometry_ms;        /* summed HIP-event times of the geometry kernels         */
+    double correlate_ms;       /* ... of the correlation kernels (direct, or CAF GEMM)   */
+    double interp_ms;          /* ... of the CAF interpolation kernels (0 for direct)    */
+    double map_ms;             /* ... of whole geoloc_map calls, first to last kernel    */
+} geoloc_plan_info;
+
+/* ABI version of the loaded library (GEOLOC_ABI_VERSION when it matches). */
+int geoloc_abi_version(void);
+
+/* Validate the descriptor, check for a gfx950 device, convert the grid to ECEF on the
+ * device (Algorithm 1, first step; sphere of radius R + h) and allocate scratch.
+ * Errors: EINVAL (n_rx < 2, a pair out of range or i == j, N % L != 0, fs or fc <= 0,
+ * empty grid, non-finite lat/lon, unknown enum), EDEVICE, ENOMEM. */
+int geoloc_plan(const geoloc_desc* desc, geoloc_plan_t* out_plan);
+
+/* Enable (nonzero) or disable per-kernel HIP-event timing of subsequent maps; either
+ * way the accumulated times in geoloc_info are reset. Events are recorded on the map's
+ * stream around each kernel launch, so the times are those of the kernels alone. */
+int geoloc_set_timing(geoloc_plan_t plan, int enable);
+
+/* Compute the map J_dev[P] (float32, DEVICE pointer owned by the caller) from the
+ * captures and receiver states (Algorithm 1: geometry, correlation, sum over steps
+ * and pairs). With GEOLOC_ACCUMULATE the result is added to J_dev, which lets a
+ * capture be processed in pieces. Asynchronous on in->stream.
+ * Errors: EINVAL (NULL pointers, non-finite state, CAF window not covering every
+ * point and step), ELAUNCH, ENOMEM. */
+int geoloc_map(geoloc_plan_t plan, const geoloc_inputs* in, float* J_dev, uint32_t flags);
+
+/* Geometry alone (Eq. (3)-(9)) for pair index e (0..n_pairs-1) and steps
+ * [step_lo, step_lo + n_steps): D_dev[k][P] = TDOA in samples, nu_dev[k][P] = FDOA in
+ * Hz, both float64 DEVICE buffers owned by the caller. Asynchronous on in->stream
+ * (in->captures is not read and may be NULL). */
+int geoloc_geometry(geoloc_plan_t plan, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo,
+                    int64_t n_steps, double* D_dev, double* nu_dev);
+
+/* Peaks of a map (the detection step at the end of Algorithm 1): the top_k largest
+ * values of J_dev[P], ties to the lowest flat index; after each peak a
+ * (2r+1) x (2r+1) window around it (RECT grids; r = nms_radius_cells) is excluded.
+ * idx_host / val_host are HOST arrays of top_k entries; fewer peaks than top_k leave
+ * idx = -1, val = -inf. Synchronises `stream`. Errors: EINVAL (top_k < 1, r < 0, r > 0
+ * on a POINTS grid), ENAN (a NaN in J), ELAUNCH. */
+int geoloc_argmax(geoloc_plan_t plan, const float* J_dev, int32_t top_k, int32_t nms_radius_cells,
+                  int64_t* idx_host, float* val_host, void* stream);
+
+int geoloc_info(geoloc_plan_t plan, geoloc_plan_info* out);
+
+/* Release the plan and its device scratch (synchronises the device first). */
+int geoloc_destroy(geoloc_plan_t plan);
+
+const char* geoloc_strerror(int status);
+const char* geoloc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEOLOC_H */

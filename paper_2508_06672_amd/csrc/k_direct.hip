@@ -1,0 +1,191 @@
+// k_direct.hip -- direct position-domain correlation in FP32 (Sec. III, Eq. (11)), with
+// the non-coherent sum over steps and pairs of Algorithm 1 fused in.
+//
+// Per candidate point p, step k and pair (i, j), with D = d0 + a and FDOA nu from the
+// FP64 geometry table:
+//   C = sum_{n in step k} y_i[n] conj(yt_j[n]) exp(+j 2 pi nu t_n),  t_n from the step centre
+//   yt_j[n] = y_j[n+d0] + a (y_j[n+d0+1] - y_j[n+d0])   (LINEAR; ROUND uses y_j[n+round(D)])
+//   J(p) += |C|^2  (or |C|).
+//
+// Mapping on gfx950 (64-wide wavefronts, 160 KiB LDS per CU):
+//  * one workgroup = 256 candidate points (a 16 x 16 cell tile of a rectilinear grid),
+//    one point per lane; a point owns its J value for the whole launch, so the sums
+//    over steps and pairs need no atomics and are deterministic;
+//  * per step the tile's lag range [dlo, dhi] is found by a wave-shuffle + LDS
+//    reduction; a sample tile of y_j[n0+dlo .. n0+T+dhi] (zero outside the capture) and
+//    y_i[n0 .. n0+T) are staged through LDS with coalesced loads; every lane then reads
+//    its own delayed taps from LDS (the second tap of the linear delay is the next
+//    sample's first tap, kept in registers) and y_i as an LDS broadcast;
+//  * the Doppler rotation uses a per-lane table E_r = exp(j 2 pi nu r / f_s),
+//    r < R, computed once per step from the FP64 FDOA, so a block of R samples needs
+//    no per-sample phasor update: C += W_b * sum_r y_i conj(yt) E_r, and the block
+//    phasor W_b advances by exp(j 2 pi nu R / f_s); W is re-anchored from an FP64 phase
+//    at the start of every LDS tile, which bounds the FP32 drift to T / R products;
+//  * a tile whose lag spread exceeds the LDS halo reads its taps from global memory
+//    (same arithmetic) instead.
+#include "internal.h"
+
+#include <climits>
+
+namespace geoloc {
+
+constexpr int kR = 16;      // samples per phasor block
+constexpr int kT = 1024;    // samples per LDS tile (multiple of kR)
+constexpr int kHalo = 512;  // largest lag spread of a tile staged in LDS
+
+// exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
+__device__ inline float2 cis_cycles(double cyc) {
+    double f = cyc - rint(cyc);
+    float s, c;
+    sincospif((float)(2.0 * f), &s, &c);
+    return make_float2(c, s);
+}
+
+__device__ inline void wg_minmax(int& lo, int& hi, int (*s_mm)[4]) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s_mm[0][w] = lo;
+        s_mm[1][w] = hi;
+    }
+    __syncthreads();
+    lo = min(min(s_mm[0][0], s_mm[0][1]), min(s_mm[0][2], s_mm[0][3]));
+    hi = max(max(s_mm[1][0], s_mm[1][1]), max(s_mm[1][2], s_mm[1][3]));
+}
+
+// One LDS tile: nblk blocks of kR samples. tap(m) returns y_j at tile offset m (relative
+// to this lane's integer delay), x[] is the staged y_i tile.
+template <bool kRound, typename Tap>
+__device__ inline void correlate_tile(const float2* __restrict__ x, int nblk, float alpha, const float2 (&E)[kR],
+                                      float2 ER, float2 W, float& cr, float& ci, Tap tap) {
+    for (int b = 0; b < nblk; ++b) {
+        const int m = b * kR;
+        float ar = 0.f, ai = 0.f;
+        float2 t0 = tap(m);
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const float2 xv = x[m + r];
+            float tr, ti;
+            if constexpr (kRound) {
+                tr = t0.x;
+                ti = t0.y;
+                if (r + 1 < kR) t0 = tap(m + r + 1);
+            } else {
+                const float2 t1 = tap(m + r + 1);
+                tr = fmaf(alpha, t1.x - t0.x, t0.x);
+                ti = fmaf(alpha, t1.y - t0.y, t0.y);
+                t0 = t1;
+            }
+            // v = y_i * E_r ; acc += v * conj(yt)
+            const float vr = fmaf(xv.x, E[r].x, -(xv.y * E[r].y));
+            const float vi = fmaf(xv.x, E[r].y, xv.y * E[r].x);
+            ar = fmaf(vi, ti, fmaf(vr, tr, ar));
+            ai = fmaf(-vr, ti, fmaf(vi, tr, ai));
+        }
+        cr = fmaf(-ai, W.y, fmaf(ar, W.x, cr));
+        ci = fmaf(ai, W.x, fmaf(ar, W.y, ci));
+        const float wr = fmaf(W.x, ER.x, -(W.y * ER.y));
+        W.y = fmaf(W.x, ER.y, W.y * ER.x);
+        W.x = wr;
+    }
+}
+
+template <bool kRound>
+__global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
+    __shared__ float2 s_y[kT + kHalo + 2];
+    __shared__ float2 s_x[kT];
+    __shared__ int s_mm[2][4];
+
+    const int tid = threadIdx.x;
+    bool valid;
+    const int64_t p = tile_point(a.tiling, blockIdx.x, tid, &valid);
+    double jacc = (valid && a.load_J) ? (double)a.J[p] : 0.0;
+    const double centre = 0.5 * (double)(a.L - 1);
+
+    for (int e = 0; e < a.n_pairs; ++e) {
+        const int2 pr = a.pairs[e];
+        const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
+        const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
+        for (int kk = 0; kk < a.kc; ++kk) {
+            const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
+            const int64_t gi = ((int64_t)e * a.kc + kk) * a.P + p;
+            double D = valid ? a.D[gi] : 0.0;
+            const double nu = valid ? a.nu[gi] : 0.0;
+            // keep the integer lag representable whatever the geometry (NaN included);
+            // such a lag lies outside any capture and reads zeros
+            if (!(fabs(D) < 1.0e9)) D = 1.0e9;
+            int d0;
+            float alpha;
+            if constexpr (kRound) {
+                d0 = (int)round(D);
+                alpha = 0.f;
+            } else {
+                const double f = floor(D);
+                d0 = (int)f;
+                alpha = (float)(D - f);
+            }
+            int dlo = valid ? d0 : INT_MAX, dhi = valid ? d0 : INT_MIN;
+            wg_minmax(dlo, dhi, s_mm);
+            const int64_t spread64 = (int64_t)dhi - (int64_t)dlo;
+            const bool in_lds = spread64 <= kHalo;
+            const int spread = in_lds ? (int)spread64 : 0;
+            const int off = valid ? d0 - dlo : 0;
+
+            const double cyc = nu * a.inv_fs;
+            float2 E[kR];
+#pragma unroll
+            for (int r = 0; r < kR; ++r) E[r] = cis_cycles(cyc * (double)r);
+            const float2 ER = cis_cycles(cyc * (double)kR);
+
+            float cr = 0.f, ci = 0.f;
+            for (int s0 = 0; s0 < a.L; s0 += kT) {
+                const int tl = min(kT, a.L - s0);
+                const int nblk = (tl + kR - 1) / kR;
+                __syncthreads();
+                for (int t = tid; t < nblk * kR; t += 256)
+                    s_x[t] = (t < tl) ? yi[n_step + s0 + t] : make_float2(0.f, 0.f);
+                if (in_lds) {
+                    const int64_t m0 = n_step + s0 + dlo;
+                    const int len = nblk * kR + spread + 1;
+                    for (int t = tid; t < len; t += 256) {
+                        const int64_t m = m0 + t;
+                        s_y[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
+                    }
+                }
+                __syncthreads();
+                const float2 W = cis_cycles(cyc * ((double)s0 - centre));
+                if (in_lds) {
+                    const float2* ys = s_y + off;
+                    correlate_tile<kRound>(s_x, nblk, alpha, E, ER, W, cr, ci, [&](int m) { return ys[m]; });
+                } else {
+                    const int64_t base = n_step + s0 + d0;
+                    const int64_t N = a.N;
+                    correlate_tile<kRound>(s_x, nblk, alpha, E, ER, W, cr, ci, [&](int m) {
+                        const int64_t q = base + m;
+                        return (q >= 0 && q < N) ? yj[q] : make_float2(0.f, 0.f);
+                    });
+                }
+            }
+            const double pw = (double)cr * cr + (double)ci * ci;
+            jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
+        }
+    }
+    if (valid) a.J[p] = (float)jacc;
+}
+
+hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s) {
+    const int64_t tiles = a.tiling.tiles_x * a.tiling.tiles_y;
+    dim3 grid((unsigned)tiles), block(256);
+    if (delay_mode == GEOLOC_DELAY_ROUND)
+        hipLaunchKernelGGL(k_direct<true>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(k_direct<false>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace geoloc

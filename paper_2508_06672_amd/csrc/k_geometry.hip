@@ -1,0 +1,78 @@
+// k_geometry.hip -- candidate grid to ECEF, and per-(pair, step, point) TDOA / FDOA in FP64.
+//
+// Grid conversion: Sec. III (candidate points given in latitude / longitude, put on the
+// surface and converted to ECEF), first step of Algorithm 1; a sphere of radius R + h.
+// Geometry: Sec. II-B, Eq. (3)-(8), delay expressed in samples as in Eq. (9):
+//   r = p_rx - q,  rho = |r|,  tau = rho / c,  f = -(1/lambda) (r / rho) . v_rx,
+//   D = (tau_j - tau_i) f_s,   nu = f_j - f_i.
+// Both kernels evaluate every product and sum as written (no contraction into FMA),
+// which keeps them bit-comparable with a plain FP64 implementation of the same
+// expressions apart from the device's sqrt / sincos rounding.
+#include "internal.h"
+
+namespace geoloc {
+
+#pragma clang fp contract(off)
+
+__global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ lat, const double* __restrict__ lon,
+                                                   int32_t grid_kind, int64_t rows, int64_t cols, double radius,
+                                                   double* __restrict__ xyz) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= rows * cols) return;
+    double la, lo;
+    if (grid_kind == GEOLOC_GRID_RECT) {
+        int64_t r = p / cols;
+        la = lat[r];
+        lo = lon[p - r * cols];
+    } else {
+        la = lat[p];
+        lo = lon[p];
+    }
+    double cl = cos(la);
+    xyz[3 * p + 0] = radius * cl * cos(lo);
+    xyz[3 * p + 1] = radius * cl * sin(lo);
+    xyz[3 * p + 2] = radius * sin(la);
+}
+
+__device__ inline void delay_doppler(const double q0, const double q1, const double q2, const double* __restrict__ s,
+                                     double inv_lambda, double* tau, double* f) {
+    double r0 = s[0] - q0, r1 = s[1] - q1, r2 = s[2] - q2;
+    double rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    *tau = rho / kLightSpeed;
+    *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
+}
+
+__global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = a.P * a.kc * a.n_pairs;
+    if (idx >= total) return;
+    int64_t p = idx % a.P;
+    int64_t rest = idx / a.P;
+    int32_t kk = (int32_t)(rest % a.kc);
+    int32_t e = (int32_t)(rest / a.kc);
+    int32_t k = a.k0 + kk;
+    int2 pr = a.pairs[e];
+    double q0 = a.xyz[3 * p], q1 = a.xyz[3 * p + 1], q2 = a.xyz[3 * p + 2];
+    double ti, fi, tj, fj;
+    delay_doppler(q0, q1, q2, a.states + ((int64_t)k * a.n_rx + pr.x) * 6, a.inv_lambda, &ti, &fi);
+    delay_doppler(q0, q1, q2, a.states + ((int64_t)k * a.n_rx + pr.y) * 6, a.inv_lambda, &tj, &fj);
+    a.D[idx] = (tj - ti) * a.fs;
+    a.nu[idx] = fj - fi;
+}
+
+hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
+                            double radius, double* xyz, hipStream_t s) {
+    int64_t P = rows * cols;
+    dim3 grid((unsigned)((P + 255) / 256));
+    hipLaunchKernelGGL(k_grid_ecef, grid, dim3(256), 0, s, lat, lon, grid_kind, rows, cols, radius, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(const GeomArgs& a, hipStream_t s) {
+    int64_t total = a.P * a.kc * a.n_pairs;
+    dim3 grid((unsigned)((total + 255) / 256));
+    hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace geoloc

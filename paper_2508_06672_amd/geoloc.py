@@ -1,0 +1,275 @@
+"""ctypes binding of libgeoloc.so -- argument marshalling only.
+
+The functions named ``geoloc_*`` mirror the C ABI in ``include/geoloc.h`` one to
+one; ``Plan`` wraps them for torch device buffers (PyTorch provides device memory
+and the stream; every step of the computation runs in the library's kernels).
+If the library is not built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgeoloc.so")
+
+ABI_VERSION = 1
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
+DIRECT_FP32, CAF_BF16, CAF_FP16 = 0, 1, 2
+DELAY_LINEAR, DELAY_ROUND = 0, 1
+ACC_POWER, ACC_MAG = 0, 1
+GRID_RECT, GRID_POINTS = 0, 1
+ACCUMULATE = 1
+
+
+class GeolocError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+
+
+class geoloc_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_rx", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("pairs", ctypes.POINTER(ctypes.c_int32)),
+        ("n_samples", ctypes.c_int64), ("step_len", ctypes.c_int64),
+        ("fs_hz", ctypes.c_double), ("fc_hz", ctypes.c_double),
+        ("grid_kind", ctypes.c_int32), ("_pad0", ctypes.c_int32),
+        ("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64),
+        ("lat", ctypes.POINTER(ctypes.c_double)), ("lon", ctypes.POINTER(ctypes.c_double)),
+        ("earth_radius_m", ctypes.c_double), ("alt_m", ctypes.c_double),
+        ("method", ctypes.c_int32), ("delay_mode", ctypes.c_int32), ("accum_mode", ctypes.c_int32),
+        ("caf_lags", ctypes.c_int32), ("caf_bins", ctypes.c_int32),
+        ("caf_lag_lo_set", ctypes.c_int32), ("caf_lag_lo", ctypes.c_int32), ("_pad1", ctypes.c_int32),
+        ("caf_nu_lo_hz", ctypes.c_double), ("caf_nu_hi_hz", ctypes.c_double),
+    ]
+
+
+class geoloc_inputs(ctypes.Structure):
+    _fields_ = [("captures", _vp), ("rx_state", ctypes.POINTER(ctypes.c_double)), ("stream", _vp)]
+
+
+class geoloc_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("n_points", ctypes.c_int64), ("n_steps", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+        ("n_samples", ctypes.c_int64), ("step_len", ctypes.c_int64),
+        ("method", ctypes.c_int32), ("delay_mode", ctypes.c_int32),
+        ("caf_lag_lo", ctypes.c_int32), ("caf_lags", ctypes.c_int32), ("caf_bins", ctypes.c_int32),
+        ("_pad", ctypes.c_int32),
+        ("caf_nu_lo_hz", ctypes.c_double), ("caf_nu_hi_hz", ctypes.c_double),
+        ("device_bytes", ctypes.c_int64), ("timed_maps", ctypes.c_int64), ("correlate_launches", ctypes.c_int64),
+        ("geometry_ms", ctypes.c_double), ("correlate_ms", ctypes.c_double), ("interp_ms", ctypes.c_double),
+        ("map_ms", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.geoloc_abi_version.restype = ctypes.c_int
+    lib.geoloc_plan.argtypes = [P(geoloc_desc), P(_vp)]
+    lib.geoloc_set_timing.argtypes = [_vp, ctypes.c_int]
+    lib.geoloc_map.argtypes = [_vp, P(geoloc_inputs), _vp, ctypes.c_uint32]
+    lib.geoloc_geometry.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp, _vp]
+    lib.geoloc_argmax.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), _vp]
+    lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
+    lib.geoloc_destroy.argtypes = [_vp]
+    lib.geoloc_strerror.argtypes = [ctypes.c_int]
+    lib.geoloc_strerror.restype = ctypes.c_char_p
+    lib.geoloc_last_error.restype = ctypes.c_char_p
+    for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_map", "geoloc_geometry", "geoloc_argmax",
+                 "geoloc_info", "geoloc_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    if lib.geoloc_abi_version() != ABI_VERSION:
+        raise ImportError(f"libgeoloc ABI {lib.geoloc_abi_version()} != binding ABI {ABI_VERSION}")
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise GeolocError(status, where, geoloc_last_error())
+
+
+# --------------------------------------------------------------------------- one-to-one calls
+
+def geoloc_abi_version() -> int:
+    return load().geoloc_abi_version()
+
+
+def geoloc_strerror(status: int) -> str:
+    return load().geoloc_strerror(status).decode()
+
+
+def geoloc_last_error() -> str:
+    return load().geoloc_last_error().decode()
+
+
+def geoloc_plan(desc: geoloc_desc) -> int:
+    h = _vp()
+    _check(load().geoloc_plan(ctypes.byref(desc), ctypes.byref(h)), "geoloc_plan")
+    return h.value
+
+
+def geoloc_set_timing(plan: int, enable: bool) -> None:
+    _check(load().geoloc_set_timing(plan, int(bool(enable))), "geoloc_set_timing")
+
+
+def geoloc_map(plan: int, inputs: geoloc_inputs, J_dev: int, flags: int = 0) -> None:
+    _check(load().geoloc_map(plan, ctypes.byref(inputs), J_dev, flags), "geoloc_map")
+
+
+def geoloc_geometry(plan: int, inputs: geoloc_inputs, pair_index: int, step_lo: int, n_steps: int,
+                    D_dev: int, nu_dev: int) -> None:
+    _check(load().geoloc_geometry(plan, ctypes.byref(inputs), pair_index, step_lo, n_steps, D_dev, nu_dev),
+           "geoloc_geometry")
+
+
+def geoloc_argmax(plan: int, J_dev: int, top_k: int, nms_radius: int, stream: int) -> Tuple[np.ndarray, np.ndarray]:
+    idx = np.empty(top_k, dtype=np.int64)
+    val = np.empty(top_k, dtype=np.float32)
+    _check(load().geoloc_argmax(plan, J_dev, top_k, nms_radius,
+                                idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream), "geoloc_argmax")
+    return idx, val
+
+
+def geoloc_info(plan: int) -> geoloc_plan_info:
+    out = geoloc_plan_info()
+    _check(load().geoloc_info(plan, ctypes.byref(out)), "geoloc_info")
+    return out
+
+
+def geoloc_destroy(plan: int) -> None:
+    _check(load().geoloc_destroy(plan), "geoloc_destroy")
+
+
+# --------------------------------------------------------------------------- torch-facing wrapper
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A plan over one grid and capture shape; maps take torch complex64 captures on the GPU."""
+
+    def __init__(self, *, n_rx: int, n_samples: int, step_len: int, fs_hz: float, fc_hz: float,
+                 lat, lon, grid_kind: int = GRID_RECT, n_rows: Optional[int] = None, n_cols: Optional[int] = None,
+                 pairs: Optional[Sequence[Tuple[int, int]]] = None, earth_radius_m: float = 6371.0e3,
+                 alt_m: float = 0.0, method: int = DIRECT_FP32, delay_mode: int = DELAY_LINEAR,
+                 accum_mode: int = ACC_POWER, caf_lags: int = 0, caf_bins: int = 0,
+                 caf_lag_lo: Optional[int] = None, caf_nu_lo_hz: float = math.nan, caf_nu_hi_hz: float = math.nan):
+        self._lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
+        self._lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
+        if grid_kind == GRID_RECT:
+            n_rows, n_cols = self._lat.size, self._lon.size
+        else:
+            if n_rows is None:
+                n_rows, n_cols = 1, self._lat.size
+        pr = np.ascontiguousarray(np.asarray(pairs if pairs else [], dtype=np.int32).reshape(-1, 2))
+        self._pairs = pr
+        d = geoloc_desc()
+        d.n_rx, d.n_pairs = n_rx, pr.shape[0]
+        d.pairs = pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if pr.size else None
+        d.n_samples, d.step_len = n_samples, step_len
+        d.fs_hz, d.fc_hz = fs_hz, fc_hz
+        d.grid_kind, d.n_rows, d.n_cols = grid_kind, n_rows, n_cols
+        d.lat = self._lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.lon = self._lon.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.earth_radius_m, d.alt_m = earth_radius_m, alt_m
+        d.method, d.delay_mode, d.accum_mode = method, delay_mode, accum_mode
+        d.caf_lags, d.caf_bins = caf_lags, caf_bins
+        d.caf_lag_lo_set = 0 if caf_lag_lo is None else 1
+        d.caf_lag_lo = 0 if caf_lag_lo is None else int(caf_lag_lo)
+        d.caf_nu_lo_hz, d.caf_nu_hi_hz = caf_nu_lo_hz, caf_nu_hi_hz
+        self.n_rx, self.n_samples, self.step_len = n_rx, n_samples, step_len
+        self.n_steps = n_samples // step_len
+        self.n_rows, self.n_cols = n_rows, n_cols
+        self.n_points = n_rows * n_cols
+        self.handle = geoloc_plan(d)
+
+    @classmethod
+    def for_scenario(cls, scn, **kw) -> "Plan":
+        wl = scn.workload
+        return cls(n_rx=wl.n_rx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                   lat=scn.lat, lon=scn.lon, pairs=list(wl.pairs), earth_radius_m=wl.earth_radius_m, **kw)
+
+    def _inputs(self, captures, states: np.ndarray, stream) -> Tuple[geoloc_inputs, np.ndarray]:
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        if st.shape != (self.n_steps, self.n_rx, 6):
+            raise ValueError(f"states shape {st.shape} != {(self.n_steps, self.n_rx, 6)}")
+        inp = geoloc_inputs()
+        if captures is not None:
+            import torch
+            if captures.dtype != torch.complex64 or not captures.is_cuda or not captures.is_contiguous():
+                raise ValueError("captures must be a contiguous complex64 CUDA tensor")
+            if tuple(captures.shape) != (self.n_rx, self.n_samples):
+                raise ValueError(f"captures shape {tuple(captures.shape)} != {(self.n_rx, self.n_samples)}")
+            inp.captures = captures.data_ptr()
+        inp.rx_state = st.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        inp.stream = _stream_handle(stream)
+        return inp, st
+
+    def map(self, captures, states: np.ndarray, J=None, accumulate: bool = False, stream=None):
+        import torch
+        if J is None:
+            J = torch.empty(self.n_points, dtype=torch.float32, device=captures.device)
+        if J.dtype != torch.float32 or not J.is_contiguous() or J.numel() != self.n_points:
+            raise ValueError("J must be a contiguous float32 tensor of n_points")
+        inp, _keep = self._inputs(captures, states, stream)
+        geoloc_map(self.handle, inp, J.data_ptr(), ACCUMULATE if accumulate else 0)
+        return J
+
+    def geometry(self, states: np.ndarray, pair_index: int = 0, step_lo: int = 0, n_steps: Optional[int] = None,
+                 device="cuda", stream=None):
+        import torch
+        n = self.n_steps - step_lo if n_steps is None else n_steps
+        D = torch.empty((n, self.n_points), dtype=torch.float64, device=device)
+        nu = torch.empty_like(D)
+        inp, _keep = self._inputs(None, states, stream)
+        geoloc_geometry(self.handle, inp, pair_index, step_lo, n, D.data_ptr(), nu.data_ptr())
+        return D, nu
+
+    def argmax(self, J, top_k: int = 1, nms_radius: int = 0, stream=None):
+        return geoloc_argmax(self.handle, J.data_ptr(), top_k, nms_radius, _stream_handle(stream))
+
+    def set_timing(self, enable: bool = True) -> None:
+        geoloc_set_timing(self.handle, enable)
+
+    def info(self) -> dict:
+        i = geoloc_info(self.handle)
+        return {f: getattr(i, f) for f, _ in geoloc_plan_info._fields_ if not f.startswith("_")}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            geoloc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,177 @@
+"""Parity of the gfx950 direct path (geometry, FP32 correlation, sum, argmax) with the
+FP64 oracle, called through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import peaks as opeaks
+from helpers import DIRECT_TOL, check_argmax, err_J, log, require_gpu
+from paper_2508_06672_amd import configs, sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2508_06672_amd import geoloc
+    geoloc.load()
+    return geoloc
+
+
+def _gpu_map(torch, G, scn, **kw):
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn, **kw) as plan:
+        J = plan.map(caps, scn.states)
+        torch.cuda.synchronize()
+        return J.cpu().numpy().astype(np.float64)
+
+
+def test_geometry_parity(torch, G):
+    for wl in (configs.SMALL, configs.MAP_1E6.with_(n_rows=37, n_cols=29, n_samples=50_000, step_len=10_000)):
+        scn = sim.make_scenario(wl, 3)
+        log(f"geometry {wl.name}")
+        xyz = oracle.grid_ecef(*sim.points_of(scn), wl.earth_radius_m)
+        Do, nuo = oracle.geometry(xyz, scn.states, (0, 1), wl.fs_hz, wl.fc_hz)
+        with G.Plan.for_scenario(scn) as plan:
+            D, nu = plan.geometry(scn.states)
+            D1, nu1 = plan.geometry(scn.states, step_lo=1, n_steps=2)
+            torch.cuda.synchronize()
+            D, nu, D1, nu1 = (t.cpu().numpy() for t in (D, nu, D1, nu1))
+        assert np.max(np.abs(D - Do)) <= 1e-8, np.max(np.abs(D - Do))
+        assert np.max(np.abs(nu - nuo)) <= 1e-8, np.max(np.abs(nu - nuo))
+        assert np.array_equal(D1, D[1:3]) and np.array_equal(nu1, nu[1:3])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_direct_parity_small(torch, G, seed):
+    scn = sim.make_scenario(configs.SMALL, seed)
+    log(f"direct small seed {seed}")
+    Jo = oracle.map_scenario(scn)
+    Jg = _gpu_map(torch, G, scn)
+    e = err_J(Jg, Jo)
+    log(f"  err_J = {e:.3g}")
+    assert e <= DIRECT_TOL
+    check_argmax(Jg, Jo, DIRECT_TOL)
+
+
+@pytest.mark.parametrize("delay,accum", [(1, 0), (0, 1), (1, 1)])
+def test_direct_modes(torch, G, delay, accum):
+    scn = sim.make_scenario(configs.SMALL.with_(n_samples=12000), 5)
+    log(f"direct modes delay={delay} accum={accum}")
+    Jo = oracle.map_scenario(scn, delay_mode=delay, accum_mode=accum)
+    Jg = _gpu_map(torch, G, scn, delay_mode=delay, accum_mode=accum)
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+    check_argmax(Jg, Jo, DIRECT_TOL)
+
+
+def test_direct_three_receivers_three_pairs(torch, G):
+    wl = configs.SMALL.with_(rx_along_track_m=(-25e3, 25e3, 0.0), rx_cross_track_m=(0.0, 0.0, 30e3),
+                             pairs=((0, 1), (2, 0), (1, 2)), n_rows=45, n_cols=38, n_samples=8000)
+    scn = sim.make_scenario(wl, 6)
+    log("direct three pairs")
+    Jo = oracle.map_scenario(scn)
+    Jg = _gpu_map(torch, G, scn)
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+    check_argmax(Jg, Jo, DIRECT_TOL)
+
+
+def test_direct_point_list_wide_lag_spread(torch, G):
+    """Random points over a 500 km footprint at 10 MHz: a 256-point tile spans more lags
+    than the LDS halo holds, which exercises the global-memory tap path."""
+    wl = configs.MAP_1E6.with_(n_samples=20_000, step_len=10_000)
+    scn = sim.make_scenario(wl, 7)
+    la, lo = sim.points_of(scn)
+    rng = np.random.Generator(np.random.PCG64(7))
+    sel = rng.choice(la.size, 1500, replace=False)
+    lat_p, lon_p = la[sel], lo[sel]
+    log("direct point list")
+    Jo = oracle.map_points(lat_p, lon_p, scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan(n_rx=2, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                lat=lat_p, lon=lon_p, grid_kind=G.GRID_POINTS) as plan:
+        D, _ = plan.geometry(scn.states)
+        spread = D.floor().cpu().numpy()
+        assert np.max(spread[:, :256].max(1) - spread[:, :256].min(1)) > 512
+        J = plan.map(caps, scn.states)
+        torch.cuda.synchronize()
+        Jg = J.cpu().numpy()
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+
+
+def test_direct_ragged_shapes(torch, G):
+    """Step length that is not a multiple of the 16-sample block nor of the LDS tile,
+    grid edges that cut 16 x 16 tiles, and delays reaching past the capture ends."""
+    wl = configs.SMALL.with_(n_rows=19, n_cols=23, n_samples=3 * 1301, step_len=1301)
+    scn = sim.make_scenario(wl, 8)
+    log("direct ragged")
+    Jo = oracle.map_scenario(scn)
+    Jg = _gpu_map(torch, G, scn)
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+    # one point, one step
+    wl1 = configs.SMALL.with_(n_rows=1, n_cols=1, n_samples=999, step_len=999)
+    scn1 = sim.make_scenario(wl1, 9)
+    Jo1 = oracle.map_scenario(scn1)
+    Jg1 = _gpu_map(torch, G, scn1)
+    assert abs(Jg1[0] - Jo1[0]) <= DIRECT_TOL * Jo1[0]
+
+
+def test_accumulate_and_determinism(torch, G):
+    scn = sim.make_scenario(configs.SMALL.with_(n_samples=8000), 10)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn) as plan:
+        J1 = plan.map(caps, scn.states).clone()
+        J2 = plan.map(caps, scn.states).clone()
+        J3 = plan.map(caps, scn.states, J=J2.clone(), accumulate=True)
+        torch.cuda.synchronize()
+    assert torch.equal(J1, J2)
+    assert torch.allclose(J3, 2 * J1, rtol=1e-6, atol=0)
+
+
+def test_argmax_rules(torch, G):
+    scn = sim.make_scenario(configs.SMALL, 0)
+    rng = np.random.Generator(np.random.PCG64(11))
+    with G.Plan.for_scenario(scn) as plan:
+        P = plan.n_points
+        for trial in range(4):
+            J = rng.integers(0, 50, P).astype(np.float32)         # many exact ties
+            idx, val = plan.argmax(torch.from_numpy(J).cuda())
+            i, v = opeaks.argmax(J)
+            assert idx[0] == i and val[0] == v
+            idx, val = plan.argmax(torch.from_numpy(J).cuda(), top_k=3, nms_radius=2)
+            ref = opeaks.topk(J, plan.n_rows, plan.n_cols, 3, 2)
+            assert list(idx) == [r[0] for r in ref]
+        J = np.ones(P, dtype=np.float32)
+        J[1234] = np.nan
+        with pytest.raises(G.GeolocError) as ei:
+            plan.argmax(torch.from_numpy(J).cuda())
+        assert ei.value.status == G.ENAN
+
+
+def test_map_1e6_sampled_points(torch, G):
+    """The full 1000 x 1000-point, 1e6-sample map in the benchmark's launch
+    configuration, checked at sampled points (random + a window around the peak)."""
+    wl = configs.MAP_1E6
+    scn = sim.make_scenario(wl, 0)
+    log("1e6 map: gpu")
+    Jg = _gpu_map(torch, G, scn)
+    ag = int(np.argmax(Jg))
+    rng = np.random.Generator(np.random.PCG64(12))
+    r0, c0 = divmod(ag, wl.n_cols)
+    win = [(r, c) for r in range(max(0, r0 - 5), min(wl.n_rows, r0 + 6))
+           for c in range(max(0, c0 - 5), min(wl.n_cols, c0 + 6))]
+    idx = np.unique(np.r_[rng.choice(wl.n_points, 256, replace=False), [r * wl.n_cols + c for r, c in win]])
+    rows, cols = np.divmod(idx, wl.n_cols)
+    log(f"1e6 map: oracle at {idx.size} points")
+    Jo = oracle.map_points(scn.lat[rows], scn.lon[cols], scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz)
+    e = float(np.max(np.abs(Jg[idx] - Jo)) / np.max(Jo))
+    log(f"1e6 map: err_J = {e:.3g}")
+    assert e <= DIRECT_TOL
+    # the peak of the sampled window is the GPU's peak within tolerance
+    assert Jo[np.searchsorted(idx, ag)] >= (1 - 2 * DIRECT_TOL) * np.max(Jo)
