@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this library has no multi-GPU path",
@@ -103,6 +105,15 @@ def main() -> int:
     from paper_2508_06672_amd import configs, geoloc, sim
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {n} bytes device to device")
+        del src, dst
     wl = configs.MAP_1E6
     log(f"simulating {wl.name} seed {args.seed}")
     scn = sim.make_scenario(wl, args.seed)

@@ -185,8 +185,10 @@ int upload_states(geoloc_plan_t p, const double* host, hipStream_t s) {
 }
 
 int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc, double* D, double* nu,
-                 hipStream_t s) {
+                 bool tile_major, hipStream_t s) {
     GeomArgs g{};
+    g.tiling = p->tiling;
+    g.tile_major = tile_major ? 1 : 0;
     g.xyz = p->d_xyz;
     g.states = p->d_states;
     g.pairs = p->d_pairs + pair_lo;
@@ -310,7 +312,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     p->tiling.tiles_x = (p->tiling.cols + p->tiling.tile_w - 1) / p->tiling.tile_w;
     p->tiling.tiles_y = (p->tiling.rows + p->tiling.tile_h - 1) / p->tiling.tile_h;
 
-    const int64_t per_step = (int64_t)p->n_pairs * P * 16;
+    const int64_t table_points = p->tiling.tiles_x * p->tiling.tiles_y * kTilePoints;  // tile-major >= P
+    const int64_t per_step = (int64_t)p->n_pairs * table_points * 16;
     int64_t kc = kGeomChunkBytes / per_step;
     if (kc < 1) kc = 1;
     if (kc > p->K) kc = p->K;
@@ -323,8 +326,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_xyz, (size_t)P * 3))) break;
         if ((rc = dev_alloc(p, &p->d_states, (size_t)p->K * p->n_rx * 6))) break;
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
-        if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * P))) break;
-        if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * P))) break;
+        if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
+        if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
         p->am.n_blocks = argmax_blocks(P);
         if ((rc = dev_alloc(p, &p->am.part_val, p->am.n_blocks))) break;
         if ((rc = dev_alloc(p, &p->am.part_idx, p->am.n_blocks))) break;
@@ -395,7 +398,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         const int32_t kc = (int32_t)std::min<int64_t>(p->kc, p->K - k0);
         TimedSpan sg{}, sc{};
         if ((rc = span_begin(p, s, &sg, 0))) return rc;
-        if ((rc = run_geometry(p, 0, p->n_pairs, k0, kc, p->d_D, p->d_nu, s))) return rc;
+        if ((rc = run_geometry(p, 0, p->n_pairs, k0, kc, p->d_D, p->d_nu, true, s))) return rc;
         if ((rc = span_end(p, s, &sg))) return rc;
 
         DirectArgs a{};
@@ -405,6 +408,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.pairs = p->d_pairs;
         a.J = J;
         a.tiling = p->tiling;
+        a.n_tiles = p->tiling.tiles_x * p->tiling.tiles_y;
         a.N = p->N;
         a.P = p->P;
         a.L = (int32_t)p->L;
@@ -435,7 +439,7 @@ int geoloc_geometry(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index
     hipStream_t s = (hipStream_t)in->stream;
     int rc = upload_states(p, in->rx_state, s);
     if (rc) return rc;
-    return run_geometry(p, pair_index, 1, step_lo, (int32_t)n_steps, D, nu, s);
+    return run_geometry(p, pair_index, 1, step_lo, (int32_t)n_steps, D, nu, false, s);
 }
 
 int geoloc_argmax(geoloc_plan_t p, const float* J, int32_t top_k, int32_t radius, int64_t* idx_host, float* val_host,

@@ -34,11 +34,12 @@ __host__ __device__ inline int64_t tile_point(const PointTiling& t, int64_t tile
 
 struct DirectArgs {
     const float2* cap;       // [n_rx][N] complex64
-    const double* D;         // [n_pairs][kc][P] delay in samples
-    const double* nu;        // [n_pairs][kc][P] FDOA in Hz
+    const double* D;         // delay in samples, tile-major (see n_tiles)
+    const double* nu;        // FDOA in Hz, tile-major
     const int2* pairs;       // [n_pairs]
     float* J;                // [P]
     PointTiling tiling;
+    int64_t n_tiles;         // tiles_x * tiles_y; D / nu are [n_pairs][kc][n_tiles][256]
     int64_t N, P;
     int32_t L, k0, kc, n_pairs;
     double inv_fs;
@@ -50,8 +51,10 @@ struct GeomArgs {
     const double* xyz;       // [P][3]
     const double* states;    // [K][n_rx][6]
     const int2* pairs;
-    double* D;               // [n_pairs][kc][P]
+    double* D;               // [n_pairs][kc][P], or tile-major [n_pairs][kc][n_tiles][256]
     double* nu;
+    PointTiling tiling;
+    int32_t tile_major;      // write the tile-major layout read by the correlation kernels
     int64_t P;
     int32_t n_rx, n_pairs, k0, kc;
     double fs, inv_lambda;

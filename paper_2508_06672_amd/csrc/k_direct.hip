@@ -11,11 +11,14 @@
 //  * one workgroup = 256 candidate points (a 16 x 16 cell tile of a rectilinear grid),
 //    one point per lane; a point owns its J value for the whole launch, so the sums
 //    over steps and pairs need no atomics and are deterministic;
+//  * the FP64 geometry table is stored tile-major, so each workgroup reads one aligned,
+//    contiguous 2 KiB run of delays and one of FDOAs per step;
 //  * per step the tile's lag range [dlo, dhi] is found by a wave-shuffle + LDS
-//    reduction; a sample tile of y_j[n0+dlo .. n0+T+dhi] (zero outside the capture) and
-//    y_i[n0 .. n0+T) are staged through LDS with coalesced loads; every lane then reads
-//    its own delayed taps from LDS (the second tap of the linear delay is the next
-//    sample's first tap, kept in registers) and y_i as an LDS broadcast;
+//    reduction; a sample tile of y_j[n0+dlo .. n0+T+dhi] (zero outside the capture) is
+//    staged through LDS with coalesced loads and every lane reads its own delayed taps
+//    from it (the second tap of the linear delay is the next sample's first tap, kept in
+//    registers); y_i, the same for every lane, comes in through scalar loads and is used
+//    as an SGPR operand, which leaves the LDS bandwidth to the taps;
 //  * the Doppler rotation uses a per-lane table E_r = exp(j 2 pi nu r / f_s),
 //    r < R, computed once per step from the FP64 FDOA, so a block of R samples needs
 //    no per-sample phasor update: C += W_b * sum_r y_i conj(yt) E_r, and the block
@@ -29,9 +32,20 @@
 
 namespace geoloc {
 
-constexpr int kR = 16;      // samples per phasor block
-constexpr int kT = 1024;    // samples per LDS tile (multiple of kR)
-constexpr int kHalo = 512;  // largest lag spread of a tile staged in LDS
+#ifndef GEOLOC_DIRECT_R
+#define GEOLOC_DIRECT_R 16
+#endif
+#ifndef GEOLOC_DIRECT_T
+#define GEOLOC_DIRECT_T 1024
+#endif
+#ifndef GEOLOC_DIRECT_WAVES_PER_EU
+#define GEOLOC_DIRECT_WAVES_PER_EU 4
+#endif
+
+constexpr int kR = GEOLOC_DIRECT_R;   // samples per phasor block
+constexpr int kT = GEOLOC_DIRECT_T;   // samples per LDS tile (multiple of kR)
+constexpr int kHalo = 512;            // largest lag spread of a tile staged in LDS
+static_assert(kT % kR == 0, "LDS tile must hold whole phasor blocks");
 
 // exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
 __device__ inline float2 cis_cycles(double cyc) {
@@ -58,25 +72,37 @@ __device__ inline void wg_minmax(int& lo, int& hi, int (*s_mm)[4]) {
     hi = max(max(s_mm[1][0], s_mm[1][1]), max(s_mm[1][2], s_mm[1][3]));
 }
 
-// One LDS tile: nblk blocks of kR samples. tap(m) returns y_j at tile offset m (relative
-// to this lane's integer delay), x[] is the staged y_i tile.
-template <bool kRound, typename Tap>
-__device__ inline void correlate_tile(const float2* __restrict__ x, int nblk, float alpha, const float2 (&E)[kR],
-                                      float2 ER, float2 W, float& cr, float& ci, Tap tap) {
-    for (int b = 0; b < nblk; ++b) {
+// Blocks [b0, b1) of one sample tile, kR samples each. xs points at y_i for the tile's
+// first sample: every lane reads the same address, so these are scalar (SGPR) loads and
+// y_i enters the FMAs as a scalar operand. tap(m) returns y_j at tile offset m relative to
+// this lane's integer delay. kTail masks samples at or beyond `tl` (last, partial block).
+template <bool kRound, bool kTail, typename Tap>
+__device__ inline void correlate_blocks(const float2* __restrict__ xs, int b0, int b1, int tl, float alpha,
+                                        const float2 (&E)[kR], float2 ER, float2& W, float& cr, float& ci,
+                                        Tap tap) {
+    for (int b = b0; b < b1; ++b) {
         const int m = b * kR;
         float ar = 0.f, ai = 0.f;
-        float2 t0 = tap(m);
+        float2 tp[kR + 1];
+#pragma unroll
+        for (int r = 0; r <= kR; ++r) tp[r] = (kRound && r == kR) ? make_float2(0.f, 0.f) : tap(m + r);
+        float2 t0 = tp[0];
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const float2 xv = x[m + r];
+            float2 xv;
+            if constexpr (kTail) {
+                xv = xs[min(m + r, tl - 1)];  // address kept inside the capture, value masked
+                if (m + r >= tl) xv = make_float2(0.f, 0.f);
+            } else {
+                xv = xs[m + r];
+            }
             float tr, ti;
             if constexpr (kRound) {
                 tr = t0.x;
                 ti = t0.y;
-                if (r + 1 < kR) t0 = tap(m + r + 1);
+                t0 = tp[r + 1];
             } else {
-                const float2 t1 = tap(m + r + 1);
+                const float2 t1 = tp[r + 1];
                 tr = fmaf(alpha, t1.x - t0.x, t0.x);
                 ti = fmaf(alpha, t1.y - t0.y, t0.y);
                 t0 = t1;
@@ -95,10 +121,19 @@ __device__ inline void correlate_tile(const float2* __restrict__ x, int nblk, fl
     }
 }
 
+template <bool kRound, typename Tap>
+__device__ inline void correlate_tile(const float2* __restrict__ xs, int tl, float alpha, const float2 (&E)[kR],
+                                      float2 ER, float2 W, float& cr, float& ci, Tap tap) {
+    const int nfull = tl / kR;
+    correlate_blocks<kRound, false>(xs, 0, nfull, tl, alpha, E, ER, W, cr, ci, tap);
+    if (nfull * kR < tl)
+        correlate_blocks<kRound, true>(xs, nfull, nfull + 1, tl, alpha, E, ER, W, cr, ci, tap);
+}
+
 template <bool kRound>
-__global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEOLOC_DIRECT_WAVES_PER_EU)))
+void k_direct(DirectArgs a) {
     __shared__ float2 s_y[kT + kHalo + 2];
-    __shared__ float2 s_x[kT];
     __shared__ int s_mm[2][4];
 
     const int tid = threadIdx.x;
@@ -113,7 +148,7 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         for (int kk = 0; kk < a.kc; ++kk) {
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-            const int64_t gi = ((int64_t)e * a.kc + kk) * a.P + p;
+            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + blockIdx.x) * kTilePoints + tid;
             double D = valid ? a.D[gi] : 0.0;
             const double nu = valid ? a.nu[gi] : 0.0;
             // keep the integer lag representable whatever the geometry (NaN included);
@@ -147,8 +182,6 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
                 const int tl = min(kT, a.L - s0);
                 const int nblk = (tl + kR - 1) / kR;
                 __syncthreads();
-                for (int t = tid; t < nblk * kR; t += 256)
-                    s_x[t] = (t < tl) ? yi[n_step + s0 + t] : make_float2(0.f, 0.f);
                 if (in_lds) {
                     const int64_t m0 = n_step + s0 + dlo;
                     const int len = nblk * kR + spread + 1;
@@ -159,13 +192,16 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
                 }
                 __syncthreads();
                 const float2 W = cis_cycles(cyc * ((double)s0 - centre));
+                const float2* xs = yi + n_step + s0;
                 if (in_lds) {
-                    const float2* ys = s_y + off;
-                    correlate_tile<kRound>(s_x, nblk, alpha, E, ER, W, cr, ci, [&](int m) { return ys[m]; });
+                    // 64-bit LDS reads (ds_read2_b64 pairs) of the complex taps
+                    const double* ys = reinterpret_cast<const double*>(s_y + off);
+                    correlate_tile<kRound>(xs, tl, alpha, E, ER, W, cr, ci,
+                                           [&](int m) { return __builtin_bit_cast(float2, ys[m]); });
                 } else {
                     const int64_t base = n_step + s0 + d0;
                     const int64_t N = a.N;
-                    correlate_tile<kRound>(s_x, nblk, alpha, E, ER, W, cr, ci, [&](int m) {
+                    correlate_tile<kRound>(xs, tl, alpha, E, ER, W, cr, ci, [&](int m) {
                         const int64_t q = base + m;
                         return (q >= 0 && q < N) ? yj[q] : make_float2(0.f, 0.f);
                     });

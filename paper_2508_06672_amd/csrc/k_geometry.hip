@@ -42,14 +42,28 @@ __device__ inline void delay_doppler(const double q0, const double q1, const dou
     *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
 }
 
+// One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
+// Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * 256 + lane, with the point of
+// (tile, lane) as in the correlation kernels; lanes past the grid edge write zeros.
 __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t total = a.P * a.kc * a.n_pairs;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * kTilePoints : a.P;
+    const int64_t total = per_step * a.kc * a.n_pairs;
     if (idx >= total) return;
-    int64_t p = idx % a.P;
-    int64_t rest = idx / a.P;
-    int32_t kk = (int32_t)(rest % a.kc);
-    int32_t e = (int32_t)(rest / a.kc);
+    const int64_t within = idx % per_step;
+    const int64_t rest = idx / per_step;
+    const int32_t kk = (int32_t)(rest % a.kc);
+    const int32_t e = (int32_t)(rest / a.kc);
+    int64_t p = within;
+    if (a.tile_major) {
+        bool valid;
+        p = tile_point(a.tiling, within / kTilePoints, (int)(within % kTilePoints), &valid);
+        if (!valid) {
+            a.D[idx] = 0.0;
+            a.nu[idx] = 0.0;
+            return;
+        }
+    }
     int32_t k = a.k0 + kk;
     int2 pr = a.pairs[e];
     double q0 = a.xyz[3 * p], q1 = a.xyz[3 * p + 1], q2 = a.xyz[3 * p + 2];
@@ -69,7 +83,8 @@ hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_k
 }
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s) {
-    int64_t total = a.P * a.kc * a.n_pairs;
+    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * kTilePoints : a.P;
+    const int64_t total = per_step * a.kc * a.n_pairs;
     dim3 grid((unsigned)((total + 255) / 256));
     hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, s, a);
     return hipGetLastError();
