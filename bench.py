@@ -83,6 +83,80 @@ def cpu_baseline(scn, seconds: float = 15.0, max_points: int = 16384):
                       f"({units:.3g} correlations in {t:.1f} s, FP64 C/OpenMP)"}
 
 
+MFMA_PEAK_TFLOPS = 2500.0         # MI355X dense BF16 / FP16 MFMA
+
+
+def cell_dist(a: int, b: int, n_cols: int) -> int:
+    ra, ca = divmod(int(a), n_cols)
+    rb, cb = divmod(int(b), n_cols)
+    return max(abs(ra - rb), abs(ca - cb))
+
+
+def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str, steps: int):
+    """Time the CAF-table map on the same inputs and compare it with the direct map."""
+    import numpy as np
+    wl = scn.workload
+    m = geoloc.CAF_BF16 if method == "bf16" else geoloc.CAF_FP16
+    plan = geoloc.Plan.for_scenario(scn, method=m)
+    J = torch.empty(wl.n_points, dtype=torch.float32, device="cuda")
+    plan.map(caps, scn.states, J=J)
+    plan.argmax(J)
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.map(caps, scn.states, J=J)
+        idx, _ = plan.argmax(J)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = plan.info()
+    Jc = J.cpu().numpy().astype(np.float64)
+    Jd = J_direct
+    flops = 8.0 * info["caf_lags"] * wl.n_samples * info["caf_bins"] * len(wl.pairs)
+    gemm_ms = info["correlate_ms"] / max(1, info["timed_maps"])
+    out = {"map_ms": ms, "speedup_vs_direct": ms_direct / ms,
+           "effective_value": wl.units / (ms / 1e3),
+           "err_vs_direct": float(np.max(np.abs(Jc - Jd)) / np.max(Jd)),
+           "argmax_cell_dist": cell_dist(idx[0], a_direct, wl.n_cols),
+           "window": {"lag_lo": info["caf_lag_lo"], "lags": info["caf_lags"], "bins": info["caf_bins"],
+                      "nu_lo_hz": info["caf_nu_lo_hz"], "nu_hi_hz": info["caf_nu_hi_hz"]},
+           "kernel_ms": {"setup": info["geometry_ms"] / max(1, info["timed_maps"]), "gemm": gemm_ms,
+                         "interp": info["interp_ms"] / max(1, info["timed_maps"])},
+           "gemm_roofline": {"bound": "mfma", "achieved": flops / (gemm_ms / 1e3) / 1e12, "peak": MFMA_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": flops / (gemm_ms / 1e3) / 1e12 / MFMA_PEAK_TFLOPS,
+                             "flop": flops}}
+    plan.close()
+    return out
+
+
+def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
+    """Fraction of seeded scenarios whose BF16 CAF peak is within one cell of the direct
+    FP32 peak, or tol-optimal on the direct map."""
+    import numpy as np
+    from paper_2508_06672_amd import sim
+    within = optimal = 0
+    for sd in seeds:
+        scn = sim.make_scenario(wl, sd)
+        caps = torch.from_numpy(scn.captures).cuda()
+        with geoloc.Plan.for_scenario(scn) as pd, geoloc.Plan.for_scenario(scn, method=geoloc.CAF_BF16) as pc:
+            Jd = pd.map(caps, scn.states)
+            ad = int(pd.argmax(Jd)[0][0])
+            Jc = pc.map(caps, scn.states)
+            ac = int(pc.argmax(Jc)[0][0])
+            Jd = Jd.cpu().numpy()
+        w = cell_dist(ac, ad, wl.n_cols) <= 1
+        o = Jd[ac] >= (1 - 2 * tol) * Jd[ad]
+        within += w
+        optimal += (w or o)
+        log(f"  agreement seed {sd}: caf {ac} direct {ad} within1={w} tol-optimal={o}")
+    n = len(seeds)
+    return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "within_one_cell": within / n,
+            "within_one_cell_or_tol_optimal": optimal / n}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +165,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-caf", action="store_true", help="skip the CAF-table legs")
+    ap.add_argument("--agreement-seeds", type=int, default=8,
+                    help="scenarios (seeds 10000..) for the CAF-vs-direct argmax agreement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -160,6 +237,18 @@ def main() -> int:
                 "kernel": "k_direct", "launch_ms": round(k_ms, 4), "units_per_launch": units_per_launch,
                 "flop_per_unit": FLOP_PER_UNIT}
 
+    caf = None
+    if not args.no_caf:
+        Jd = J.cpu().numpy().astype(np.float64)
+        ad = int(idx[0])
+        caf = {}
+        for m in ("bf16", "fp16"):
+            log(f"caf leg {m}")
+            caf[m] = caf_leg(geoloc, torch, scn, caps, Jd, ad, ms, m, args.steps)
+        if args.agreement_seeds > 0:
+            log(f"caf agreement over {args.agreement_seeds} seeds")
+            caf["agreement_bf16"] = agreement(geoloc, torch, wl, list(range(10000, 10000 + args.agreement_seeds)))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scn, args.cpu_seconds)
@@ -178,6 +267,7 @@ def main() -> int:
         "h2d_ms": h2d_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "caf": caf,
     }
     print(json.dumps(out), flush=True)
     plan.close()

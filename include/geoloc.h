@@ -144,7 +144,16 @@ int geoloc_set_timing(geoloc_plan_t plan, int enable);
 /* Compute the map J_dev[P] (float32, DEVICE pointer owned by the caller) from the
  * captures and receiver states (Algorithm 1: geometry, correlation, sum over steps
  * and pairs). With GEOLOC_ACCUMULATE the result is added to J_dev, which lets a
- * capture be processed in pieces. Asynchronous on in->stream.
+ * capture be processed in pieces. Asynchronous on in->stream for GEOLOC_DIRECT_FP32;
+ * the CAF methods synchronise the stream once per map to size (or validate) the table
+ * window from the footprint's delay and Doppler extent, then run asynchronously.
+ * CAF window (Sec. I's cross-ambiguity function, one table per step and pair):
+ *   lags  lag_lo .. lag_lo + caf_lags - 1: fitted to [floor(min D) - 1, floor(max D) + 2]
+ *         unless caf_lags / caf_lag_lo are given (then they must cover it);
+ *   bins  caf_bins centres nu_lo + m dnu, dnu = (nu_hi - nu_lo) / (caf_bins - 1), fitted to
+ *         [min nu - dnu, min nu + (caf_bins - 2) dnu] unless caf_nu_lo_hz / caf_nu_hi_hz
+ *         are given (then [min nu, max nu] must lie inside). Each point reads its table by
+ *         bilinear interpolation in (delay, Doppler).
  * Errors: EINVAL (NULL pointers, non-finite state, CAF window not covering every
  * point and step), ELAUNCH, ENOMEM. */
 int geoloc_map(geoloc_plan_t plan, const geoloc_inputs* in, float* J_dev, uint32_t flags);
@@ -155,6 +164,15 @@ int geoloc_map(geoloc_plan_t plan, const geoloc_inputs* in, float* J_dev, uint32
  * (in->captures is not read and may be NULL). */
 int geoloc_geometry(geoloc_plan_t plan, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo,
                     int64_t n_steps, double* D_dev, double* nu_dev);
+
+/* CAF tables alone (CAF methods only; the window is fitted or validated as in
+ * geoloc_map): T_dev[k][d][m] = sum over step step_lo + k of y_i[n] conj(y_j[n + lag_lo + d])
+ * exp(+j 2 pi nu_m t_n), nu_m = nu_lo + m (nu_hi - nu_lo) / (bins - 1), t_n from the step
+ * centre; complex64 interleaved DEVICE buffer of n_steps * caf_lags * caf_bins entries owned
+ * by the caller (the window actually used is reported by geoloc_info). Pair index e as in
+ * geoloc_geometry. Synchronises in->stream once to size the window. */
+int geoloc_caf_table(geoloc_plan_t plan, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo,
+                     int64_t n_steps, void* T_dev, int64_t T_capacity);
 
 /* Peaks of a map (the detection step at the end of Algorithm 1): the top_k largest
  * values of J_dev[P], ties to the lowest flat index; after each peak a

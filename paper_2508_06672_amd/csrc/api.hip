@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,6 +66,27 @@ struct geoloc_plan_s {
     double* h_states = nullptr;
     hipEvent_t states_copied = nullptr;
     bool states_pending = false;
+    // CAF table path
+    int32_t caf_lags_req = 0, caf_bins = 256, caf_lag_lo_req = 0;
+    bool caf_lag_lo_set = false;
+    double caf_nu_lo_req = NAN, caf_nu_hi_req = NAN;
+    int64_t caf_lag_lo = 0;
+    int32_t caf_n_lags = 0, caf_n_lags_pad = 0, caf_M_pad = 0, caf_L_pad = 0;
+    double caf_nu_lo = NAN, caf_nu_hi = NAN, caf_dnu = 0;
+    int32_t caf_scale_exp = 0;
+    unsigned short* d_Fr = nullptr;
+    unsigned short* d_Fi = nullptr;
+    size_t F_elems = 0;
+    bool F_valid = false;
+    double F_nu_lo = 0, F_dnu = 0;
+    int32_t F_M = 0, F_L = 0;
+    float2* d_T = nullptr;
+    size_t T_elems = 0;
+    float2* d_Tpart = nullptr;
+    size_t Tpart_elems = 0;
+    double* d_part = nullptr;
+    double* h_part = nullptr;
+    int32_t part_elems = 0;
     // timing
     bool timing = false;
     std::vector<TimedSpan> spans;
@@ -113,6 +135,12 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->am.part_idx);
     (void)hipFree(p->am.found_idx);
     (void)hipFree(p->am.found_val);
+    (void)hipFree(p->d_Fr);
+    (void)hipFree(p->d_Fi);
+    (void)hipFree(p->d_T);
+    (void)hipFree(p->d_Tpart);
+    (void)hipFree(p->d_part);
+    if (p->h_part) (void)hipHostFree(p->h_part);
     if (p->h_states) (void)hipHostFree(p->h_states);
     if (p->states_copied) (void)hipEventDestroy(p->states_copied);
     for (auto& s : p->spans) {
@@ -205,6 +233,229 @@ int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, 
     return GEOLOC_OK;
 }
 
+constexpr int64_t kCafTableBytes = 1ll << 30;   // budget for one step-chunk of CAF tables
+constexpr int32_t kCafPowerBlocks = 64;
+
+// Grow-only device buffer.
+template <typename T>
+int ensure(geoloc_plan_t p, T** buf, size_t* cap, size_t need) {
+    if (*cap >= need && *buf) return GEOLOC_OK;
+    if (*buf) {
+        (void)hipFree(*buf);
+        p->device_bytes -= (int64_t)(*cap * sizeof(T));
+        *buf = nullptr;
+        *cap = 0;
+    }
+    int rc = dev_alloc(p, buf, need);
+    if (rc) return rc;
+    *cap = need;
+    return GEOLOC_OK;
+}
+
+CafGeomArgs caf_geom(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs) {
+    CafGeomArgs g{};
+    g.xyz = p->d_xyz;
+    g.states = p->d_states;
+    g.pairs = p->d_pairs + pair_lo;
+    g.P = p->P;
+    g.K = (int32_t)p->K;
+    g.n_rx = p->n_rx;
+    g.n_pairs = n_pairs;
+    g.fs = p->fs;
+    g.inv_lambda = p->fc / kLightSpeed;
+    return g;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Size (or validate) the CAF window from the footprint's delay / Doppler extent, choose the
+// input scale, and (re)build the phasor table. Synchronises stream s once.
+int caf_prepare(geoloc_plan_t p, const float2* cap, hipStream_t s) {
+    const bool f16 = p->method == GEOLOC_CAF_FP16;
+    CafGeomArgs g = caf_geom(p, 0, p->n_pairs);
+    const int32_t eb = caf_extent_blocks(p->P * p->K * p->n_pairs);
+    const int32_t need = eb * 4 + kCafPowerBlocks * p->n_rx;
+    if (p->part_elems < need) {
+        (void)hipFree(p->d_part);
+        if (p->h_part) (void)hipHostFree(p->h_part);
+        p->d_part = nullptr;
+        p->h_part = nullptr;
+        int rc = dev_alloc(p, &p->d_part, (size_t)need);
+        if (rc) return rc;
+        if (hipHostMalloc((void**)&p->h_part, need * sizeof(double)) != hipSuccess) {
+            p->h_part = nullptr;
+            return fail(GEOLOC_ENOMEM, "pinned host allocation failed");
+        }
+        p->part_elems = need;
+    }
+    HIP_TRY(launch_caf_extent(g, p->d_part, eb, s));
+    HIP_TRY(launch_caf_power(cap, p->N, p->n_rx, p->d_part + eb * 4, kCafPowerBlocks, s));
+    HIP_TRY(hipMemcpyAsync(p->h_part, p->d_part, need * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double dmin = INFINITY, dmax = -INFINITY, nmin = INFINITY, nmax = -INFINITY, pw = 0.0;
+    for (int b = 0; b < eb; ++b) {
+        dmin = std::min(dmin, p->h_part[4 * b]);
+        dmax = std::max(dmax, -p->h_part[4 * b + 1]);
+        nmin = std::min(nmin, p->h_part[4 * b + 2]);
+        nmax = std::max(nmax, -p->h_part[4 * b + 3]);
+    }
+    for (int b = 0; b < kCafPowerBlocks * p->n_rx; ++b) pw += p->h_part[eb * 4 + b];
+    if (!std::isfinite(dmin) || !std::isfinite(dmax) || !std::isfinite(nmin) || !std::isfinite(nmax) ||
+        std::fabs(dmin) > 1e9 || std::fabs(dmax) > 1e9)
+        return fail(GEOLOC_EINVAL, "geometry out of range for a CAF table (D in [%g, %g], nu in [%g, %g])", dmin,
+                    dmax, nmin, nmax);
+    // lag window
+    const int64_t need_lo = (int64_t)std::floor(dmin) - 1, need_hi = (int64_t)std::floor(dmax) + 2;
+    const int64_t n_lags = p->caf_lags_req > 0 ? p->caf_lags_req : need_hi - need_lo + 1;
+    int64_t lag_lo = need_lo;
+    if (p->caf_lag_lo_set)
+        lag_lo = p->caf_lag_lo_req;
+    else if (p->caf_lags_req > 0)
+        lag_lo = (int64_t)std::floor(0.5 * (dmin + dmax)) - n_lags / 2;
+    if (lag_lo > need_lo || lag_lo + n_lags - 1 < need_hi)
+        return fail(GEOLOC_EINVAL, "CAF lag window [%lld, %lld] does not cover the footprint's [%lld, %lld]",
+                    (long long)lag_lo, (long long)(lag_lo + n_lags - 1), (long long)need_lo, (long long)need_hi);
+    if (n_lags > (1 << 20) || lag_lo < INT32_MIN / 2 || lag_lo > INT32_MAX / 2)
+        return fail(GEOLOC_EINVAL, "CAF lag window too large");
+    // Doppler bins
+    const int32_t M = p->caf_bins;
+    double lo, hi, dnu;
+    if (std::isfinite(p->caf_nu_lo_req) && std::isfinite(p->caf_nu_hi_req)) {
+        lo = p->caf_nu_lo_req;
+        hi = p->caf_nu_hi_req;
+        dnu = (hi - lo) / (M - 1);
+        if (!(hi > lo) || nmin < lo || nmax > hi)
+            return fail(GEOLOC_EINVAL, "CAF Doppler window [%g, %g] Hz does not cover the footprint's [%g, %g] Hz", lo,
+                        hi, nmin, nmax);
+    } else {
+        dnu = std::max(nmax - nmin, 1.0) / (M - 3);
+        lo = nmin - dnu;
+        hi = lo + (M - 1) * dnu;
+    }
+    p->caf_lag_lo = lag_lo;
+    p->caf_n_lags = (int32_t)n_lags;
+    p->caf_n_lags_pad = (int32_t)round_up(n_lags, 64);
+    p->caf_M_pad = (int32_t)round_up(M, 256);
+    p->caf_L_pad = (int32_t)round_up(p->L, 16);
+    p->caf_nu_lo = lo;
+    p->caf_nu_hi = hi;
+    p->caf_dnu = dnu;
+    // power-of-two input scale: lag products near unit magnitude (keeps FP16 in range)
+    const double mean_pw = pw / ((double)p->N * p->n_rx);
+    int32_t se = mean_pw > 0 ? (int32_t)std::lround(std::log2(mean_pw)) : 0;
+    p->caf_scale_exp = std::min(60, std::max(-60, se));
+    // phasor table
+    const size_t felems = (size_t)p->caf_L_pad * p->caf_M_pad;
+    if (!p->F_valid || p->F_nu_lo != lo || p->F_dnu != dnu || p->F_M != M || p->F_L != p->L) {
+        size_t cap_r = p->F_elems, cap_i = p->F_elems;
+        int rc = ensure(p, &p->d_Fr, &cap_r, felems);
+        if (rc) return rc;
+        rc = ensure(p, &p->d_Fi, &cap_i, felems);
+        if (rc) return rc;
+        p->F_elems = std::min(cap_r, cap_i);
+        HIP_TRY(launch_caf_phasor(f16, p->caf_L_pad, (int32_t)p->L, M, p->caf_M_pad, lo, dnu, 1.0 / p->fs, p->d_Fr,
+                                  p->d_Fi, s));
+        p->F_valid = true;
+        p->F_nu_lo = lo;
+        p->F_dnu = dnu;
+        p->F_M = M;
+        p->F_L = (int32_t)p->L;
+    }
+    return GEOLOC_OK;
+}
+
+// Work split of the CAF GEMM for n_pairs pairs: steps per chunk and split-K of each step.
+void caf_split(geoloc_plan_t p, int32_t n_pairs, int64_t n_steps, int32_t* kc_out, int32_t* n_split_out,
+               int32_t* chunk_out) {
+    const int64_t per_step = (int64_t)n_pairs * p->caf_n_lags_pad * p->caf_M_pad * 8;
+    int64_t kc = std::max<int64_t>(1, std::min<int64_t>(n_steps, kCafTableBytes / per_step));
+    const int64_t wgs = (int64_t)(p->caf_n_lags_pad / 64) * (p->caf_M_pad / 256) * n_pairs * kc;
+    int64_t n_split = 1, chunk = p->L;
+    if (wgs < 1024) {
+        n_split = std::min<int64_t>((1024 + wgs - 1) / wgs, (p->L + 255) / 256);
+        chunk = round_up((p->L + n_split - 1) / n_split, 256);
+        n_split = (p->L + chunk - 1) / chunk;
+        while (n_split > 1 && per_step * kc * n_split > kCafTableBytes) {
+            chunk *= 2;
+            n_split = (p->L + chunk - 1) / chunk;
+        }
+    }
+    *kc_out = (int32_t)kc;
+    *n_split_out = (int32_t)n_split;
+    *chunk_out = (int32_t)chunk;
+}
+
+// CAF tables of pairs [pair_lo, pair_lo + n_pairs) for steps [k0, k0 + kc) into p->d_T.
+int caf_tables(geoloc_plan_t p, const float2* cap, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc,
+               int32_t n_split, int32_t chunk, hipStream_t s) {
+    const bool f16 = p->method == GEOLOC_CAF_FP16;
+    const size_t tel = (size_t)n_pairs * kc * p->caf_n_lags_pad * p->caf_M_pad;
+    int rc = ensure(p, &p->d_T, &p->T_elems, tel);
+    if (rc) return rc;
+    if (n_split > 1 && (rc = ensure(p, &p->d_Tpart, &p->Tpart_elems, tel * n_split))) return rc;
+    CafGemmArgs a{};
+    a.cap = cap;
+    a.pairs = p->d_pairs + pair_lo;
+    a.Fr = p->d_Fr;
+    a.Fi = p->d_Fi;
+    a.out = n_split > 1 ? p->d_Tpart : p->d_T;
+    a.N = p->N;
+    a.L = (int32_t)p->L;
+    a.k0 = (int32_t)k0;
+    a.kc = kc;
+    a.n_pairs = n_pairs;
+    a.n_split = n_split;
+    a.chunk = chunk;
+    a.lag_lo = (int32_t)p->caf_lag_lo;
+    a.n_lags_pad = p->caf_n_lags_pad;
+    a.M_pad = p->caf_M_pad;
+    a.scale = std::ldexp(1.0f, -p->caf_scale_exp);
+    const float unscale = std::ldexp(1.0f, p->caf_scale_exp);
+    a.unscale = n_split > 1 ? 1.0f : unscale;
+    HIP_TRY(launch_caf_gemm(f16, a, s));
+    if (n_split > 1) HIP_TRY(launch_caf_reduce(p->d_Tpart, (int64_t)tel, n_split, unscale, p->d_T, s));
+    return GEOLOC_OK;
+}
+
+int caf_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flags, hipStream_t s) {
+    const float2* cap = (const float2*)in->captures;
+    TimedSpan sp{};
+    int rc = span_begin(p, s, &sp, 0);
+    if (rc) return rc;
+    if ((rc = caf_prepare(p, cap, s))) return rc;
+    if ((rc = span_end(p, s, &sp))) return rc;
+    int32_t kc, n_split, chunk;
+    caf_split(p, p->n_pairs, p->K, &kc, &n_split, &chunk);
+    for (int64_t k0 = 0; k0 < p->K; k0 += kc) {
+        const int32_t kn = (int32_t)std::min<int64_t>(kc, p->K - k0);
+        TimedSpan sg{}, si{};
+        if ((rc = span_begin(p, s, &sg, 1))) return rc;
+        if ((rc = caf_tables(p, cap, 0, p->n_pairs, k0, kn, n_split, chunk, s))) return rc;
+        if ((rc = span_end(p, s, &sg))) return rc;
+        if (p->timing) p->correlate_launches++;
+        CafInterpArgs a{};
+        a.g = caf_geom(p, 0, p->n_pairs);
+        a.tiling = p->tiling;
+        a.T = p->d_T;
+        a.J = J;
+        a.lag_lo = p->caf_lag_lo;
+        a.n_lags = p->caf_n_lags;
+        a.n_lags_pad = p->caf_n_lags_pad;
+        a.M = p->caf_bins;
+        a.M_pad = p->caf_M_pad;
+        a.k0 = (int32_t)k0;
+        a.kc = kn;
+        a.nu_lo = p->caf_nu_lo;
+        a.dnu = p->caf_dnu;
+        a.accum_mode = p->accum_mode;
+        a.load_J = (k0 > 0) || (flags & GEOLOC_ACCUMULATE);
+        if ((rc = span_begin(p, s, &si, 2))) return rc;
+        HIP_TRY(launch_caf_interp(a, p->delay_mode, s));
+        if ((rc = span_end(p, s, &si))) return rc;
+    }
+    return GEOLOC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -272,7 +523,17 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if (!std::isfinite(d->lat[i])) return fail(GEOLOC_EINVAL, "lat[%lld] not finite", (long long)i);
     for (int64_t i = 0; i < n_lon; ++i)
         if (!std::isfinite(d->lon[i])) return fail(GEOLOC_EINVAL, "lon[%lld] not finite", (long long)i);
-    if (d->method != GEOLOC_DIRECT_FP32) return fail(GEOLOC_EUNSUPPORTED, "CAF methods are not built yet");
+    if (d->method != GEOLOC_DIRECT_FP32) {
+        if (d->caf_bins != 0 && (d->caf_bins < 4 || d->caf_bins > 65536))
+            return fail(GEOLOC_EINVAL, "caf_bins must be 0 or in [4, 65536]");
+        if (d->caf_lags < 0 || (d->caf_lags > 0 && d->caf_lags < 3) || d->caf_lags > (1 << 20))
+            return fail(GEOLOC_EINVAL, "caf_lags must be 0 or in [3, 2^20]");
+        if (std::isfinite(d->caf_nu_lo_hz) != std::isfinite(d->caf_nu_hi_hz))
+            return fail(GEOLOC_EINVAL, "give both caf_nu_lo_hz and caf_nu_hi_hz, or neither");
+        if (std::isfinite(d->caf_nu_lo_hz) && !(d->caf_nu_hi_hz > d->caf_nu_lo_hz))
+            return fail(GEOLOC_EINVAL, "caf_nu_hi_hz must exceed caf_nu_lo_hz");
+        if (d->step_len > (1ll << 28)) return fail(GEOLOC_EINVAL, "step_len too long for a CAF table");
+    }
 
     int dev = 0;
     int rc = check_device(&dev);
@@ -296,6 +557,12 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     p->cols = d->n_cols;
     p->fs = d->fs_hz;
     p->fc = d->fc_hz;
+    p->caf_lags_req = d->caf_lags;
+    p->caf_bins = d->caf_bins > 0 ? d->caf_bins : 256;
+    p->caf_lag_lo_set = d->caf_lag_lo_set != 0;
+    p->caf_lag_lo_req = d->caf_lag_lo;
+    p->caf_nu_lo_req = d->caf_nu_lo_hz;
+    p->caf_nu_hi_req = d->caf_nu_hi_hz;
     p->radius = d->earth_radius_m;
     p->alt = d->alt_m;
     if (d->grid_kind == GEOLOC_GRID_RECT) {
@@ -394,6 +661,12 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
     if (rc) return rc;
     TimedSpan whole{};
     if ((rc = span_begin(p, s, &whole, 3))) return rc;
+    if (p->method != GEOLOC_DIRECT_FP32) {
+        if ((rc = caf_map(p, in, J, flags, s))) return rc;
+        if ((rc = span_end(p, s, &whole))) return rc;
+        if (p->timing) p->timed_maps++;
+        return GEOLOC_OK;
+    }
     for (int64_t k0 = 0; k0 < p->K; k0 += p->kc) {
         const int32_t kc = (int32_t)std::min<int64_t>(p->kc, p->K - k0);
         TimedSpan sg{}, sc{};
@@ -442,6 +715,39 @@ int geoloc_geometry(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index
     return run_geometry(p, pair_index, 1, step_lo, (int32_t)n_steps, D, nu, false, s);
 }
 
+int geoloc_caf_table(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo, int64_t n_steps,
+                     void* T_dev, int64_t T_capacity) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (p->method == GEOLOC_DIRECT_FP32) return fail(GEOLOC_EINVAL, "geoloc_caf_table needs a CAF method");
+    if (!in || !in->captures || !in->rx_state || !T_dev) return fail(GEOLOC_EINVAL, "NULL input or output");
+    if (((uintptr_t)in->captures & 7) != 0 || ((uintptr_t)T_dev & 7) != 0)
+        return fail(GEOLOC_EINVAL, "captures and T_dev must be 8-byte aligned");
+    if (pair_index < 0 || pair_index >= p->n_pairs) return fail(GEOLOC_EINVAL, "pair_index out of range");
+    if (step_lo < 0 || n_steps < 1 || step_lo + n_steps > p->K)
+        return fail(GEOLOC_EINVAL, "step range outside [0, %lld)", (long long)p->K);
+    hipStream_t s = (hipStream_t)in->stream;
+    int rc = upload_states(p, in->rx_state, s);
+    if (rc) return rc;
+    const float2* cap = (const float2*)in->captures;
+    if ((rc = caf_prepare(p, cap, s))) return rc;
+    const int64_t per = (int64_t)p->caf_n_lags * p->caf_bins;
+    if (T_capacity < per * n_steps)
+        return fail(GEOLOC_EINVAL, "T_capacity %lld < %lld entries needed", (long long)T_capacity,
+                    (long long)(per * n_steps));
+    int32_t kc, n_split, chunk;
+    caf_split(p, 1, n_steps, &kc, &n_split, &chunk);
+    for (int64_t k = 0; k < n_steps; k += kc) {
+        const int32_t kn = (int32_t)std::min<int64_t>(kc, n_steps - k);
+        if ((rc = caf_tables(p, cap, pair_index, 1, step_lo + k, kn, n_split, chunk, s))) return rc;
+        for (int32_t q = 0; q < kn; ++q)
+            HIP_TRY(hipMemcpy2DAsync((float2*)T_dev + (k + q) * per, (size_t)p->caf_bins * sizeof(float2),
+                                     p->d_T + (size_t)q * p->caf_n_lags_pad * p->caf_M_pad,
+                                     (size_t)p->caf_M_pad * sizeof(float2), (size_t)p->caf_bins * sizeof(float2),
+                                     (size_t)p->caf_n_lags, hipMemcpyDeviceToDevice, s));
+    }
+    return GEOLOC_OK;
+}
+
 int geoloc_argmax(geoloc_plan_t p, const float* J, int32_t top_k, int32_t radius, int64_t* idx_host, float* val_host,
                   void* stream) {
     if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
@@ -477,8 +783,11 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.step_len = p->L;
     r.method = p->method;
     r.delay_mode = p->delay_mode;
-    r.caf_nu_lo_hz = NAN;
-    r.caf_nu_hi_hz = NAN;
+    r.caf_lag_lo = (int32_t)p->caf_lag_lo;
+    r.caf_lags = p->caf_n_lags;
+    r.caf_bins = p->method == GEOLOC_DIRECT_FP32 ? 0 : p->caf_bins;
+    r.caf_nu_lo_hz = p->caf_nu_lo;
+    r.caf_nu_hi_hz = p->caf_nu_hi;
     r.device_bytes = p->device_bytes;
     r.timed_maps = p->timed_maps;
     r.correlate_launches = p->correlate_launches;

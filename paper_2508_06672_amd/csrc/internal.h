@@ -60,6 +60,66 @@ struct GeomArgs {
     double fs, inv_lambda;
 };
 
+// Delay and Doppler of one receiver state s = [p; v] against ECEF point q (Sec. II-B,
+// Eq. (3)-(6)): rho = |p - q|, tau = rho / c, f = -(1/lambda) (p - q)/rho . v. Every product
+// and sum is evaluated as written (no FMA contraction).
+__device__ inline void delay_doppler(double q0, double q1, double q2, const double* __restrict__ s, double inv_lambda,
+                                     double* tau, double* f) {
+#pragma clang fp contract(off)
+    const double r0 = s[0] - q0, r1 = s[1] - q1, r2 = s[2] - q2;
+    const double rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    *tau = rho / kLightSpeed;
+    *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
+}
+
+// Everything the CAF kernels need to evaluate the geometry of (point, step, pair) inline.
+struct CafGeomArgs {
+    const double* xyz;       // [P][3]
+    const double* states;    // [K][n_rx][6]
+    const int2* pairs;       // [n_pairs]
+    int64_t P;
+    int32_t K, n_rx, n_pairs, _pad;
+    double fs, inv_lambda;
+};
+
+// TDOA in samples and FDOA in Hz of pair e at point p and step k (Eq. (7)-(9)).
+__device__ inline void pair_delay_doppler(const CafGeomArgs& g, int64_t p, int32_t k, int32_t e, double* D,
+                                          double* nu) {
+#pragma clang fp contract(off)
+    const int2 pr = g.pairs[e];
+    const double q0 = g.xyz[3 * p], q1 = g.xyz[3 * p + 1], q2 = g.xyz[3 * p + 2];
+    double ti, fi, tj, fj;
+    delay_doppler(q0, q1, q2, g.states + ((int64_t)k * g.n_rx + pr.x) * 6, g.inv_lambda, &ti, &fi);
+    delay_doppler(q0, q1, q2, g.states + ((int64_t)k * g.n_rx + pr.y) * 6, g.inv_lambda, &tj, &fj);
+    *D = (tj - ti) * g.fs;
+    *nu = fj - fi;
+}
+
+struct CafGemmArgs {
+    const float2* cap;             // [n_rx][N]
+    const int2* pairs;
+    const unsigned short* Fr;      // phasor table planes, [L_pad / 8][M_pad][8] 16-bit floats
+    const unsigned short* Fi;
+    float2* out;                   // [n_split][n_pairs * kc][n_lags_pad][M_pad]
+    int64_t N;
+    int32_t L, k0, kc, n_pairs;
+    int32_t n_split, chunk;        // split of each step's samples (chunk is a multiple of 256)
+    int32_t lag_lo, n_lags_pad, M_pad;
+    float scale, unscale;          // input scale 2^-s applied to y_i; output multiplied by unscale
+};
+
+struct CafInterpArgs {
+    CafGeomArgs g;
+    PointTiling tiling;
+    const float2* T;               // [n_pairs * kc][n_lags_pad][M_pad]
+    float* J;
+    int64_t lag_lo;
+    int32_t n_lags, n_lags_pad, M, M_pad;
+    int32_t k0, kc;
+    double nu_lo, dnu;
+    int32_t accum_mode, load_J;
+};
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
                             double radius, double* xyz, hipStream_t s);
@@ -77,5 +137,14 @@ constexpr int kMaxTopK = 64;
 hipError_t launch_argmax(const float* J, int64_t P, int64_t cols, int32_t rect, int32_t radius, int32_t top_k,
                          ArgmaxScratch& s, hipStream_t st);
 int32_t argmax_blocks(int64_t P);
+
+int32_t caf_extent_blocks(int64_t total);
+hipError_t launch_caf_extent(const CafGeomArgs& a, double* part, int32_t blocks, hipStream_t s);
+hipError_t launch_caf_power(const float2* cap, int64_t N, int32_t n_rx, double* part, int32_t blocks, hipStream_t s);
+hipError_t launch_caf_phasor(bool f16, int32_t L_pad, int32_t L, int32_t M, int32_t M_pad, double nu_lo, double dnu,
+                             double inv_fs, unsigned short* Fr, unsigned short* Fi, hipStream_t s);
+hipError_t launch_caf_gemm(bool f16, const CafGemmArgs& a, hipStream_t s);
+hipError_t launch_caf_reduce(const float2* part, int64_t n, int32_t n_split, float unscale, float2* T, hipStream_t s);
+hipError_t launch_caf_interp(const CafInterpArgs& a, int32_t delay_mode, hipStream_t s);
 
 }  // namespace geoloc

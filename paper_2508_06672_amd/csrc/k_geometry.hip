@@ -34,14 +34,6 @@ __global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ la
     xyz[3 * p + 2] = radius * sin(la);
 }
 
-__device__ inline void delay_doppler(const double q0, const double q1, const double q2, const double* __restrict__ s,
-                                     double inv_lambda, double* tau, double* f) {
-    double r0 = s[0] - q0, r1 = s[1] - q1, r2 = s[2] - q2;
-    double rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-    *tau = rho / kLightSpeed;
-    *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
-}
-
 // One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
 // Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * 256 + lane, with the point of
 // (tile, lane) as in the correlation kernels; lanes past the grid edge write zeros.

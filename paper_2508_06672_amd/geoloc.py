@@ -86,13 +86,15 @@ def load() -> ctypes.CDLL:
     lib.geoloc_set_timing.argtypes = [_vp, ctypes.c_int]
     lib.geoloc_map.argtypes = [_vp, P(geoloc_inputs), _vp, ctypes.c_uint32]
     lib.geoloc_geometry.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp, _vp]
+    lib.geoloc_caf_table.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp,
+                                     ctypes.c_int64]
     lib.geoloc_argmax.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), _vp]
     lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
     lib.geoloc_destroy.argtypes = [_vp]
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
     lib.geoloc_strerror.restype = ctypes.c_char_p
     lib.geoloc_last_error.restype = ctypes.c_char_p
-    for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_map", "geoloc_geometry", "geoloc_argmax",
+    for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
                  "geoloc_info", "geoloc_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.geoloc_abi_version() != ABI_VERSION:
@@ -138,6 +140,12 @@ def geoloc_geometry(plan: int, inputs: geoloc_inputs, pair_index: int, step_lo: 
                     D_dev: int, nu_dev: int) -> None:
     _check(load().geoloc_geometry(plan, ctypes.byref(inputs), pair_index, step_lo, n_steps, D_dev, nu_dev),
            "geoloc_geometry")
+
+
+def geoloc_caf_table(plan: int, inputs: geoloc_inputs, pair_index: int, step_lo: int, n_steps: int, T_dev: int,
+                     T_capacity: int) -> None:
+    _check(load().geoloc_caf_table(plan, ctypes.byref(inputs), pair_index, step_lo, n_steps, T_dev, T_capacity),
+           "geoloc_caf_table")
 
 
 def geoloc_argmax(plan: int, J_dev: int, top_k: int, nms_radius: int, stream: int) -> Tuple[np.ndarray, np.ndarray]:
@@ -246,6 +254,18 @@ class Plan:
         inp, _keep = self._inputs(None, states, stream)
         geoloc_geometry(self.handle, inp, pair_index, step_lo, n, D.data_ptr(), nu.data_ptr())
         return D, nu
+
+    def caf_table(self, captures, states: np.ndarray, pair_index: int = 0, step_lo: int = 0,
+                  n_steps: Optional[int] = None, max_entries: Optional[int] = None, stream=None):
+        """CAF tables [n_steps][lags][bins] complex64 (the window is reported by info())."""
+        import torch
+        n = self.n_steps - step_lo if n_steps is None else n_steps
+        cap = max_entries if max_entries is not None else n * (1 << 22)
+        T = torch.empty(cap, dtype=torch.complex64, device=captures.device)
+        inp, _keep = self._inputs(captures, states, stream)
+        geoloc_caf_table(self.handle, inp, pair_index, step_lo, n, T.data_ptr(), cap)
+        i = geoloc_info(self.handle)
+        return T[: n * i.caf_lags * i.caf_bins].view(n, i.caf_lags, i.caf_bins)
 
     def argmax(self, J, top_k: int = 1, nms_radius: int = 0, stream=None):
         return geoloc_argmax(self.handle, J.data_ptr(), top_k, nms_radius, _stream_handle(stream))
