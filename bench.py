@@ -120,7 +120,8 @@ def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str
     out = {"map_ms": ms, "speedup_vs_direct": ms_direct / ms,
            "effective_value": wl.units / (ms / 1e3),
            "err_vs_direct": float(np.max(np.abs(Jc - Jd)) / np.max(Jd)),
-           "argmax_cell_dist": cell_dist(idx[0], a_direct, wl.n_cols),
+           "argmax_cell_dist": min(cell_dist(idx[0], a_direct, wl.n_cols),
+                                   cell_dist(idx[0], mirror_cell(scn, a_direct), wl.n_cols)),
            "window": {"lag_lo": info["caf_lag_lo"], "lags": info["caf_lags"], "bins": info["caf_bins"],
                       "nu_lo_hz": info["caf_nu_lo_hz"], "nu_hi_hz": info["caf_nu_hi_hz"]},
            "kernel_ms": {"setup": info["geometry_ms"] / max(1, info["timed_maps"]), "gemm": gemm_ms,
@@ -132,9 +133,19 @@ def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str
     return out
 
 
+def mirror_cell(scn, a: int) -> int:
+    """Grid cell of the reflection of cell a through the receivers' orbital plane: with
+    every receiver in that plane and a non-rotating Earth, J(a) = J(mirror(a)) exactly."""
+    from paper_2508_06672_amd import sim
+    r, c = divmod(int(a), scn.lon.size)
+    mr, mc = sim.nearest_cell(scn.lat, scn.lon, *sim.mirror_latlon(scn.workload, scn.lat[r], scn.lon[c]))
+    return mr * scn.lon.size + mc
+
+
 def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
     """Fraction of seeded scenarios whose BF16 CAF peak is within one cell of the direct
-    FP32 peak, or tol-optimal on the direct map."""
+    FP32 peak or of its orbital-plane mirror (an exact tie of the map), and the fraction
+    where it is at least tol-optimal on the direct map."""
     import numpy as np
     from paper_2508_06672_amd import sim
     within = optimal = 0
@@ -147,13 +158,13 @@ def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
             Jc = pc.map(caps, scn.states)
             ac = int(pc.argmax(Jc)[0][0])
             Jd = Jd.cpu().numpy()
-        w = cell_dist(ac, ad, wl.n_cols) <= 1
+        w = min(cell_dist(ac, ad, wl.n_cols), cell_dist(ac, mirror_cell(scn, ad), wl.n_cols)) <= 1
         o = Jd[ac] >= (1 - 2 * tol) * Jd[ad]
         within += w
         optimal += (w or o)
         log(f"  agreement seed {sd}: caf {ac} direct {ad} within1={w} tol-optimal={o}")
     n = len(seeds)
-    return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "within_one_cell": within / n,
+    return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "within_one_cell_or_mirror": within / n,
             "within_one_cell_or_tol_optimal": optimal / n}
 
 
@@ -196,6 +207,7 @@ def main() -> int:
     scn = sim.make_scenario(wl, args.seed)
     pinned = torch.from_numpy(scn.captures).pin_memory()
     caps = torch.empty(pinned.shape, dtype=torch.complex64, device="cuda")
+    caps.copy_(pinned, non_blocking=True)      # first copy pays one-time set-up costs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     caps.copy_(pinned, non_blocking=True)

@@ -136,6 +136,12 @@ int geoloc_abi_version(void);
  * empty grid, non-finite lat/lon, unknown enum), EDEVICE, ENOMEM. */
 int geoloc_plan(const geoloc_desc* desc, geoloc_plan_t* out_plan);
 
+/* Replace the grid coordinates of a plan (same grid kind and shape: RECT lat[n_rows],
+ * lon[n_cols]; POINTS lat[P], lon[P]; host arrays, radians) and redo the ECEF conversion.
+ * Synchronises the device; a previously fitted CAF window is refitted on the next map.
+ * Errors: EINVAL (NULL or non-finite coordinates), ELAUNCH. */
+int geoloc_set_grid(geoloc_plan_t plan, const double* lat, const double* lon);
+
 /* Enable (nonzero) or disable per-kernel HIP-event timing of subsequent maps; either
  * way the accumulated times in geoloc_info are reset. Events are recorded on the map's
  * stream around each kernel launch, so the times are those of the kernels alone. */
@@ -190,6 +196,62 @@ int geoloc_destroy(geoloc_plan_t plan);
 
 const char* geoloc_strerror(int status);
 const char* geoloc_last_error(void);
+
+/* ------------------------------------------------------------------------------------
+ * Learned tile proposal. Not part of the paper: a small CNN reads a coarse map of the
+ * same method (the map evaluated at coarse cell centres) and scores the tiles of the
+ * fine grid, so that only the most likely tiles are mapped at full resolution; the
+ * full-grid map stays the fallback and the reference. Network: `layers` 3x3
+ * convolutions (zero padding 1) with bias, ReLU between layers, channels in_ch ->
+ * hidden -> ... -> hidden -> 1, output = tile logits [height][width]; softmax over all
+ * tiles; cross-entropy against a label distribution. Parameters: one flat float vector
+ * [W0, b0, W1, b1, ...], W_l laid out [C_out][C_in][3][3]. The device keeps FP32 master
+ * parameters (updated by Adam) and an FP16 working copy used by forward and backward;
+ * activations and accumulations are FP32. Tensors are NCHW float32 DEVICE buffers owned
+ * by the caller. A handle holds the activations of its last forward for backward.
+ * ------------------------------------------------------------------------------------ */
+typedef struct geoloc_cnn_s* geoloc_cnn_t;
+
+typedef struct geoloc_cnn_desc {
+    int32_t in_ch;       /* input channels (1..32); geoloc_cnn_prepare produces 3    */
+    int32_t hidden;      /* hidden channels (1..32)                                   */
+    int32_t layers;      /* convolution layers (>= 2)                                 */
+    int32_t height, width;  /* tile grid, e.g. 64 x 64                                */
+    int32_t max_batch;   /* largest batch passed to forward / backward                */
+} geoloc_cnn_desc;
+
+/* Allocate a network with all parameters zero (uniform tile probabilities). EINVAL for
+ * out-of-range sizes, EDEVICE without a gfx950 device, ENOMEM. */
+int geoloc_cnn_create(const geoloc_cnn_desc* desc, geoloc_cnn_t* out);
+int geoloc_cnn_param_count(geoloc_cnn_t cnn, int64_t* n_params);
+/* Load n FP32 parameters from a HOST array (master and FP16 copy); resets Adam. */
+int geoloc_cnn_set_params(geoloc_cnn_t cnn, const float* theta_host, int64_t n);
+/* Copy parameters to a HOST array: which = 0 FP32 master, 1 FP16 working copy (widened),
+ * 2 last gradient. Synchronises the device. */
+int geoloc_cnn_get_params(geoloc_cnn_t cnn, int32_t which, float* out_host, int64_t n);
+/* Input features of a batch of coarse maps (in_ch must be 3): J_dev [batch][H*W] float,
+ * D_dev / nu_dev [batch][H*W] float64 TDOA (samples) and FDOA (Hz) of one reference step
+ * at the same points; x_dev [batch][3][H][W] = [log(J / mean J) clipped to +-8, D / 64,
+ * (nu - mean nu) / 256]. */
+int geoloc_cnn_prepare(geoloc_cnn_t cnn, const float* J_dev, const double* D_dev, const double* nu_dev,
+                       int32_t batch, float* x_dev, void* stream);
+/* logits_dev [batch][H][W] from x_dev [batch][in_ch][H][W]; keeps activations. */
+int geoloc_cnn_forward(geoloc_cnn_t cnn, const float* x_dev, int32_t batch, float* logits_dev, void* stream);
+/* Softmax cross-entropy per sample: loss_dev[batch], dlogits_dev = (softmax - label)/batch;
+ * label_dev [batch][H*W] sums to 1 per sample. */
+int geoloc_cnn_loss(geoloc_cnn_t cnn, const float* logits_dev, const float* label_dev, int32_t batch,
+                    float* dlogits_dev, float* loss_dev, void* stream);
+/* Parameter gradient of the loss (overwritten) from dlogits and the last forward's
+ * activations (same batch). */
+int geoloc_cnn_backward(geoloc_cnn_t cnn, const float* dlogits_dev, int32_t batch, void* stream);
+/* One Adam step on the FP32 master parameters with the last gradient, then refresh the
+ * FP16 copy: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, w -= lr m^ / (sqrt(v^) + eps). */
+int geoloc_cnn_adam_step(geoloc_cnn_t cnn, float lr, float beta1, float beta2, float eps, void* stream);
+/* The k (<= 64) highest-scoring tiles of each sample and their softmax probabilities
+ * into HOST arrays [batch][k] (ties to the lower tile index). Synchronises `stream`. */
+int geoloc_cnn_topk(geoloc_cnn_t cnn, const float* logits_dev, int32_t batch, int32_t k, int32_t* tiles_host,
+                    float* probs_host, void* stream);
+int geoloc_cnn_destroy(geoloc_cnn_t cnn);
 
 #ifdef __cplusplus
 }

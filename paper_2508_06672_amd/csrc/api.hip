@@ -56,6 +56,8 @@ struct geoloc_plan_s {
     int32_t kc = 1;  // steps per geometry chunk
     // device scratch
     double* d_xyz = nullptr;
+    double* d_lat = nullptr;         // grid coordinates as given (kept for geoloc_set_grid)
+    double* d_lon = nullptr;
     double* d_states = nullptr;
     int2* d_pairs = nullptr;
     double* d_D = nullptr;
@@ -127,6 +129,8 @@ int dev_alloc(geoloc_plan_t p, T** out, size_t count) {
 void release(geoloc_plan_t p) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_xyz);
+    (void)hipFree(p->d_lat);
+    (void)hipFree(p->d_lon);
     (void)hipFree(p->d_states);
     (void)hipFree(p->d_pairs);
     (void)hipFree(p->d_D);
@@ -587,8 +591,6 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     const int64_t n_chunks = (p->K + kc - 1) / kc;
     p->kc = (int32_t)((p->K + n_chunks - 1) / n_chunks);
 
-    double* d_lat = nullptr;
-    double* d_lon = nullptr;
     do {
         if ((rc = dev_alloc(p, &p->d_xyz, (size_t)P * 3))) break;
         if ((rc = dev_alloc(p, &p->d_states, (size_t)p->K * p->n_rx * 6))) break;
@@ -609,35 +611,44 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
             rc = fail(GEOLOC_ELAUNCH, "hipEventCreate failed");
             break;
         }
-        // grid -> ECEF on the device, once per plan
-        if ((rc = dev_alloc(p, &d_lat, (size_t)n_lat))) break;
-        if ((rc = dev_alloc(p, &d_lon, (size_t)n_lon))) break;
-        hipError_t e = hipMemcpy(d_lat, d->lat, n_lat * sizeof(double), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(d_lon, d->lon, n_lon * sizeof(double), hipMemcpyHostToDevice);
+        // grid -> ECEF on the device, once per plan (and again on geoloc_set_grid)
+        if ((rc = dev_alloc(p, &p->d_lat, (size_t)n_lat))) break;
+        if ((rc = dev_alloc(p, &p->d_lon, (size_t)n_lon))) break;
+        hipError_t e = hipMemcpy(p->d_lat, d->lat, n_lat * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_lon, d->lon, n_lon * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_grid_ecef(d_lat, d_lon, d->grid_kind, d->n_rows, d->n_cols, d->earth_radius_m + d->alt_m,
-                                 p->d_xyz, nullptr);
+            e = launch_grid_ecef(p->d_lat, p->d_lon, d->grid_kind, d->n_rows, d->n_cols,
+                                 d->earth_radius_m + d->alt_m, p->d_xyz, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             rc = fail(GEOLOC_ELAUNCH, "plan set-up: %s", hipGetErrorString(e));
             break;
         }
     } while (0);
-    if (d_lat) {
-        (void)hipFree(d_lat);
-        p->device_bytes -= n_lat * sizeof(double);
-    }
-    if (d_lon) {
-        (void)hipFree(d_lon);
-        p->device_bytes -= n_lon * sizeof(double);
-    }
     if (rc) {
         release(p);
         return rc;
     }
     *out = p;
+    return GEOLOC_OK;
+}
+
+int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (!lat || !lon) return fail(GEOLOC_EINVAL, "NULL lat or lon");
+    const int64_t n_lat = p->grid_kind == GEOLOC_GRID_RECT ? p->rows : p->P;
+    const int64_t n_lon = p->grid_kind == GEOLOC_GRID_RECT ? p->cols : p->P;
+    for (int64_t i = 0; i < n_lat; ++i)
+        if (!std::isfinite(lat[i])) return fail(GEOLOC_EINVAL, "lat[%lld] not finite", (long long)i);
+    for (int64_t i = 0; i < n_lon; ++i)
+        if (!std::isfinite(lon[i])) return fail(GEOLOC_EINVAL, "lon[%lld] not finite", (long long)i);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(p->d_lat, lat, n_lat * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_lon, lon, n_lon * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->radius + p->alt, p->d_xyz, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
     return GEOLOC_OK;
 }
 
@@ -796,6 +807,252 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.interp_ms = p->t_interp;
     r.map_ms = p->t_map;
     *out = r;
+    return GEOLOC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------ CNN
+
+struct geoloc_cnn_s {
+    uint32_t magic = 0x636e6e31u;  // "cnn1"
+    int32_t in_ch = 0, hidden = 0, layers = 0, H = 0, W = 0, max_batch = 0;
+    int64_t n_params = 0, step = 0;
+    std::vector<int32_t> cin, cout;
+    std::vector<int64_t> w_off, b_off;
+    float* d_master = nullptr;
+    float* d_grad = nullptr;
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    _Float16* d_w16 = nullptr;
+    float* d_x = nullptr;            // copy of the last forward input
+    std::vector<float*> d_z;         // pre-activations of layers 0 .. layers-2
+    float* d_g0 = nullptr;
+    float* d_g1 = nullptr;
+    int32_t* d_tiles = nullptr;
+    float* d_probs = nullptr;
+    int32_t last_batch = -1;
+};
+
+namespace {
+
+bool cnn_ok(geoloc_cnn_t c) { return c != nullptr && c->magic == 0x636e6e31u; }
+
+void cnn_release(geoloc_cnn_t c) {
+    (void)hipDeviceSynchronize();
+    for (void* ptr : {(void*)c->d_master, (void*)c->d_grad, (void*)c->d_m, (void*)c->d_v, (void*)c->d_w16,
+                      (void*)c->d_x, (void*)c->d_g0, (void*)c->d_g1, (void*)c->d_tiles, (void*)c->d_probs})
+        (void)hipFree(ptr);
+    for (float* z : c->d_z) (void)hipFree(z);
+    c->magic = 0;
+    delete c;
+}
+
+template <typename T>
+int cnn_alloc(T** out, size_t count) {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, (count ? count : 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GEOLOC_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    *out = (T*)ptr;
+    return GEOLOC_OK;
+}
+
+int cnn_batch_ok(geoloc_cnn_t c, int32_t batch) {
+    if (batch < 1 || batch > c->max_batch)
+        return fail(GEOLOC_EINVAL, "batch %d outside [1, %d]", batch, c->max_batch);
+    return GEOLOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int geoloc_cnn_create(const geoloc_cnn_desc* d, geoloc_cnn_t* out) {
+    if (!d || !out) return fail(GEOLOC_EINVAL, "NULL descriptor or output");
+    if (d->in_ch < 1 || d->in_ch > 32 || d->hidden < 1 || d->hidden > 32 || d->layers < 2 || d->layers > 16 ||
+        d->height < 1 || d->width < 1 || (int64_t)d->height * d->width > (1 << 20) || d->max_batch < 1 ||
+        d->max_batch > 4096)
+        return fail(GEOLOC_EINVAL, "CNN sizes out of range");
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    geoloc_cnn_t c = new (std::nothrow) geoloc_cnn_s();
+    if (!c) return fail(GEOLOC_ENOMEM, "host allocation failed");
+    c->in_ch = d->in_ch;
+    c->hidden = d->hidden;
+    c->layers = d->layers;
+    c->H = d->height;
+    c->W = d->width;
+    c->max_batch = d->max_batch;
+    int64_t o = 0;
+    for (int l = 0; l < c->layers; ++l) {
+        const int ci = l == 0 ? c->in_ch : c->hidden, co = l == c->layers - 1 ? 1 : c->hidden;
+        c->cin.push_back(ci);
+        c->cout.push_back(co);
+        c->w_off.push_back(o);
+        o += (int64_t)co * ci * 9;
+        c->b_off.push_back(o);
+        o += co;
+    }
+    c->n_params = o;
+    const size_t plane = (size_t)c->H * c->W;
+    do {
+        if ((rc = cnn_alloc(&c->d_master, o)) || (rc = cnn_alloc(&c->d_grad, o)) || (rc = cnn_alloc(&c->d_m, o)) ||
+            (rc = cnn_alloc(&c->d_v, o)) || (rc = cnn_alloc(&c->d_w16, o)) ||
+            (rc = cnn_alloc(&c->d_x, (size_t)c->max_batch * c->in_ch * plane)) ||
+            (rc = cnn_alloc(&c->d_g0, (size_t)c->max_batch * c->hidden * plane)) ||
+            (rc = cnn_alloc(&c->d_g1, (size_t)c->max_batch * c->hidden * plane)) ||
+            (rc = cnn_alloc(&c->d_tiles, (size_t)c->max_batch * 64)) ||
+            (rc = cnn_alloc(&c->d_probs, (size_t)c->max_batch * 64)))
+            break;
+        for (int l = 0; l + 1 < c->layers && !rc; ++l) {
+            float* z = nullptr;
+            rc = cnn_alloc(&z, (size_t)c->max_batch * c->hidden * plane);
+            if (!rc) c->d_z.push_back(z);
+        }
+        if (rc) break;
+        hipError_t e = hipMemset(c->d_master, 0, o * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(c->d_grad, 0, o * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(c->d_m, 0, o * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(c->d_v, 0, o * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(c->d_w16, 0, o * sizeof(_Float16));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = fail(GEOLOC_ELAUNCH, "CNN set-up: %s", hipGetErrorString(e));
+    } while (0);
+    if (rc) {
+        cnn_release(c);
+        return rc;
+    }
+    *out = c;
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_param_count(geoloc_cnn_t c, int64_t* n) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!n) return fail(GEOLOC_EINVAL, "NULL output");
+    *n = c->n_params;
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_set_params(geoloc_cnn_t c, const float* theta, int64_t n) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!theta || n != c->n_params) return fail(GEOLOC_EINVAL, "expected %lld parameters", (long long)c->n_params);
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(theta[i])) return fail(GEOLOC_EINVAL, "parameter %lld not finite", (long long)i);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c->d_master, theta, n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(c->d_m, 0, n * sizeof(float)));
+    HIP_TRY(hipMemset(c->d_v, 0, n * sizeof(float)));
+    HIP_TRY(launch_cnn_to_half(c->d_master, c->d_w16, n, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    c->step = 0;
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_get_params(geoloc_cnn_t c, int32_t which, float* out, int64_t n) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!out || n != c->n_params || which < 0 || which > 2) return fail(GEOLOC_EINVAL, "bad arguments");
+    HIP_TRY(hipDeviceSynchronize());
+    if (which == 1) {
+        std::vector<_Float16> h(n);
+        HIP_TRY(hipMemcpy(h.data(), c->d_w16, n * sizeof(_Float16), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) out[i] = (float)h[i];
+        return GEOLOC_OK;
+    }
+    HIP_TRY(hipMemcpy(out, which == 0 ? c->d_master : c->d_grad, n * sizeof(float), hipMemcpyDeviceToHost));
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_prepare(geoloc_cnn_t c, const float* J, const double* D, const double* nu, int32_t batch, float* x,
+                       void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (c->in_ch != 3) return fail(GEOLOC_EINVAL, "geoloc_cnn_prepare makes 3 input channels");
+    if (!J || !D || !nu || !x) return fail(GEOLOC_EINVAL, "NULL pointer");
+    if (batch < 1) return fail(GEOLOC_EINVAL, "batch < 1");
+    HIP_TRY(launch_cnn_prep(J, D, nu, c->H * c->W, batch, x, (hipStream_t)stream));
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_forward(geoloc_cnn_t c, const float* x, int32_t batch, float* logits, void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!x || !logits) return fail(GEOLOC_EINVAL, "NULL pointer");
+    int rc = cnn_batch_ok(c, batch);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t plane = (size_t)c->H * c->W;
+    HIP_TRY(hipMemcpyAsync(c->d_x, x, (size_t)batch * c->in_ch * plane * sizeof(float), hipMemcpyDeviceToDevice, s));
+    for (int l = 0; l < c->layers; ++l) {
+        const float* in = l == 0 ? c->d_x : c->d_z[l - 1];
+        float* out = l == c->layers - 1 ? logits : c->d_z[l];
+        HIP_TRY(launch_cnn_conv_fwd(l > 0, in, c->d_w16 + c->w_off[l], c->d_w16 + c->b_off[l], out, batch, c->cin[l],
+                                    c->cout[l], c->H, c->W, s));
+    }
+    c->last_batch = batch;
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_loss(geoloc_cnn_t c, const float* logits, const float* label, int32_t batch, float* dlogits,
+                    float* loss, void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!logits || !label || !dlogits || !loss) return fail(GEOLOC_EINVAL, "NULL pointer");
+    if (batch < 1) return fail(GEOLOC_EINVAL, "batch < 1");
+    HIP_TRY(launch_cnn_softmax_ce(logits, label, c->H * c->W, batch, dlogits, loss, (hipStream_t)stream));
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_backward(geoloc_cnn_t c, const float* dlogits, int32_t batch, void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!dlogits) return fail(GEOLOC_EINVAL, "NULL pointer");
+    if (batch != c->last_batch) return fail(GEOLOC_ESTATE, "backward needs the batch of the last forward");
+    hipStream_t s = (hipStream_t)stream;
+    const float* g = dlogits;
+    float* bufs[2] = {c->d_g0, c->d_g1};
+    for (int l = c->layers - 1; l >= 0; --l) {
+        const float* in = l == 0 ? c->d_x : c->d_z[l - 1];
+        HIP_TRY(launch_cnn_conv_wgrad(l > 0, g, in, c->d_grad + c->w_off[l], c->d_grad + c->b_off[l], batch,
+                                      c->cin[l], c->cout[l], c->H, c->W, s));
+        if (l > 0) {
+            float* gn = bufs[l & 1];
+            HIP_TRY(launch_cnn_conv_dgrad(true, g, c->d_w16 + c->w_off[l], c->d_z[l - 1], gn, batch, c->cin[l],
+                                          c->cout[l], c->H, c->W, s));
+            g = gn;
+        }
+    }
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_adam_step(geoloc_cnn_t c, float lr, float b1, float b2, float eps, void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!(lr > 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+        return fail(GEOLOC_EINVAL, "bad Adam hyper-parameters");
+    c->step++;
+    const float bc1 = (float)(1.0 - std::pow((double)b1, (double)c->step));
+    const float bc2 = (float)(1.0 - std::pow((double)b2, (double)c->step));
+    HIP_TRY(launch_cnn_adam(c->d_master, c->d_m, c->d_v, c->d_grad, c->d_w16, c->n_params, lr, b1, b2, eps, bc1, bc2,
+                            (hipStream_t)stream));
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_topk(geoloc_cnn_t c, const float* logits, int32_t batch, int32_t k, int32_t* tiles, float* probs,
+                    void* stream) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    if (!logits || !tiles || !probs) return fail(GEOLOC_EINVAL, "NULL pointer");
+    int rc = cnn_batch_ok(c, batch);
+    if (rc) return rc;
+    if (k < 1 || k > 64 || k > c->H * c->W) return fail(GEOLOC_EINVAL, "k must be in [1, min(64, tiles)]");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_cnn_topk(logits, c->H * c->W, batch, k, c->d_tiles, c->d_probs, s));
+    HIP_TRY(hipMemcpyAsync(tiles, c->d_tiles, (size_t)batch * k * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(probs, c->d_probs, (size_t)batch * k * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return GEOLOC_OK;
+}
+
+int geoloc_cnn_destroy(geoloc_cnn_t c) {
+    if (!cnn_ok(c)) return fail(GEOLOC_ESTATE, "invalid CNN handle");
+    cnn_release(c);
     return GEOLOC_OK;
 }
 

@@ -147,4 +147,17 @@ hipError_t launch_caf_gemm(bool f16, const CafGemmArgs& a, hipStream_t s);
 hipError_t launch_caf_reduce(const float2* part, int64_t n, int32_t n_split, float unscale, float2* T, hipStream_t s);
 hipError_t launch_caf_interp(const CafInterpArgs& a, int32_t delay_mode, hipStream_t s);
 
+hipError_t launch_cnn_conv_fwd(bool relu_in, const float* in, const _Float16* w, const _Float16* b, float* out, int B,
+                               int C, int O, int H, int W, hipStream_t s);
+hipError_t launch_cnn_conv_dgrad(bool mask, const float* g, const _Float16* w, const float* zprev, float* gin, int B,
+                                 int C, int O, int H, int W, hipStream_t s);
+hipError_t launch_cnn_conv_wgrad(bool relu_in, const float* g, const float* in, float* dw, float* db, int B, int C,
+                                 int O, int H, int W, hipStream_t s);
+hipError_t launch_cnn_softmax_ce(const float* z, const float* q, int T, int B, float* dz, float* loss, hipStream_t s);
+hipError_t launch_cnn_adam(float* master, float* m, float* v, const float* g, _Float16* w16, int64_t n, float lr,
+                           float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_cnn_to_half(const float* src, _Float16* dst, int64_t n, hipStream_t s);
+hipError_t launch_cnn_topk(const float* z, int T, int B, int k, int32_t* tiles, float* probs, hipStream_t s);
+hipError_t launch_cnn_prep(const float* J, const double* D, const double* nu, int T, int B, float* x, hipStream_t s);
+
 }  // namespace geoloc

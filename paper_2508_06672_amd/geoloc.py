@@ -70,6 +70,11 @@ class geoloc_plan_info(ctypes.Structure):
     ]
 
 
+class geoloc_cnn_desc(ctypes.Structure):
+    _fields_ = [("in_ch", ctypes.c_int32), ("hidden", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -84,6 +89,7 @@ def load() -> ctypes.CDLL:
     lib.geoloc_abi_version.restype = ctypes.c_int
     lib.geoloc_plan.argtypes = [P(geoloc_desc), P(_vp)]
     lib.geoloc_set_timing.argtypes = [_vp, ctypes.c_int]
+    lib.geoloc_set_grid.argtypes = [_vp, P(ctypes.c_double), P(ctypes.c_double)]
     lib.geoloc_map.argtypes = [_vp, P(geoloc_inputs), _vp, ctypes.c_uint32]
     lib.geoloc_geometry.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp, _vp]
     lib.geoloc_caf_table.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp,
@@ -94,8 +100,24 @@ def load() -> ctypes.CDLL:
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
     lib.geoloc_strerror.restype = ctypes.c_char_p
     lib.geoloc_last_error.restype = ctypes.c_char_p
-    for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
+    for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
                  "geoloc_info", "geoloc_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
+    lib.geoloc_cnn_param_count.argtypes = [_vp, P(i64)]
+    lib.geoloc_cnn_set_params.argtypes = [_vp, P(f32), i64]
+    lib.geoloc_cnn_get_params.argtypes = [_vp, i32, P(f32), i64]
+    lib.geoloc_cnn_prepare.argtypes = [_vp, _vp, _vp, _vp, i32, _vp, _vp]
+    lib.geoloc_cnn_forward.argtypes = [_vp, _vp, i32, _vp, _vp]
+    lib.geoloc_cnn_loss.argtypes = [_vp, _vp, _vp, i32, _vp, _vp, _vp]
+    lib.geoloc_cnn_backward.argtypes = [_vp, _vp, i32, _vp]
+    lib.geoloc_cnn_adam_step.argtypes = [_vp, f32, f32, f32, f32, _vp]
+    lib.geoloc_cnn_topk.argtypes = [_vp, _vp, i32, i32, P(i32), P(f32), _vp]
+    lib.geoloc_cnn_destroy.argtypes = [_vp]
+    for name in ("geoloc_cnn_create", "geoloc_cnn_param_count", "geoloc_cnn_set_params", "geoloc_cnn_get_params",
+                 "geoloc_cnn_prepare", "geoloc_cnn_forward", "geoloc_cnn_loss", "geoloc_cnn_backward",
+                 "geoloc_cnn_adam_step", "geoloc_cnn_topk", "geoloc_cnn_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.geoloc_abi_version() != ABI_VERSION:
         raise ImportError(f"libgeoloc ABI {lib.geoloc_abi_version()} != binding ABI {ABI_VERSION}")
@@ -130,6 +152,13 @@ def geoloc_plan(desc: geoloc_desc) -> int:
 
 def geoloc_set_timing(plan: int, enable: bool) -> None:
     _check(load().geoloc_set_timing(plan, int(bool(enable))), "geoloc_set_timing")
+
+
+def geoloc_set_grid(plan: int, lat: np.ndarray, lon: np.ndarray) -> None:
+    la = np.ascontiguousarray(lat, dtype=np.float64)
+    lo = np.ascontiguousarray(lon, dtype=np.float64)
+    _check(load().geoloc_set_grid(plan, la.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  lo.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "geoloc_set_grid")
 
 
 def geoloc_map(plan: int, inputs: geoloc_inputs, J_dev: int, flags: int = 0) -> None:
@@ -211,6 +240,7 @@ class Plan:
         self.n_steps = n_samples // step_len
         self.n_rows, self.n_cols = n_rows, n_cols
         self.n_points = n_rows * n_cols
+        self.grid_kind = grid_kind
         self.handle = geoloc_plan(d)
 
     @classmethod
@@ -270,6 +300,15 @@ class Plan:
     def argmax(self, J, top_k: int = 1, nms_radius: int = 0, stream=None):
         return geoloc_argmax(self.handle, J.data_ptr(), top_k, nms_radius, _stream_handle(stream))
 
+    def set_grid(self, lat, lon) -> None:
+        lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
+        lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
+        want = (self.n_rows, self.n_cols) if self.grid_kind == GRID_RECT else (self.n_points, self.n_points)
+        if (lat.size, lon.size) != want:
+            raise ValueError(f"grid coordinates {(lat.size, lon.size)} != {want}")
+        geoloc_set_grid(self.handle, lat, lon)
+        self._lat, self._lon = lat, lon
+
     def set_timing(self, enable: bool = True) -> None:
         geoloc_set_timing(self.handle, enable)
 
@@ -293,3 +332,125 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# --------------------------------------------------------------------------- learned tile proposal
+
+def geoloc_cnn_create(desc: geoloc_cnn_desc) -> int:
+    h = _vp()
+    _check(load().geoloc_cnn_create(ctypes.byref(desc), ctypes.byref(h)), "geoloc_cnn_create")
+    return h.value
+
+
+def geoloc_cnn_param_count(cnn: int) -> int:
+    n = ctypes.c_int64()
+    _check(load().geoloc_cnn_param_count(cnn, ctypes.byref(n)), "geoloc_cnn_param_count")
+    return n.value
+
+
+def geoloc_cnn_set_params(cnn: int, theta: np.ndarray) -> None:
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    _check(load().geoloc_cnn_set_params(cnn, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), t.size),
+           "geoloc_cnn_set_params")
+
+
+def geoloc_cnn_get_params(cnn: int, which: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float32)
+    _check(load().geoloc_cnn_get_params(cnn, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n),
+           "geoloc_cnn_get_params")
+    return out
+
+
+def geoloc_cnn_prepare(cnn: int, J_dev: int, D_dev: int, nu_dev: int, batch: int, x_dev: int, stream: int) -> None:
+    _check(load().geoloc_cnn_prepare(cnn, J_dev, D_dev, nu_dev, batch, x_dev, stream), "geoloc_cnn_prepare")
+
+
+def geoloc_cnn_forward(cnn: int, x_dev: int, batch: int, logits_dev: int, stream: int) -> None:
+    _check(load().geoloc_cnn_forward(cnn, x_dev, batch, logits_dev, stream), "geoloc_cnn_forward")
+
+
+def geoloc_cnn_loss(cnn: int, logits_dev: int, label_dev: int, batch: int, dlogits_dev: int, loss_dev: int,
+                    stream: int) -> None:
+    _check(load().geoloc_cnn_loss(cnn, logits_dev, label_dev, batch, dlogits_dev, loss_dev, stream), "geoloc_cnn_loss")
+
+
+def geoloc_cnn_backward(cnn: int, dlogits_dev: int, batch: int, stream: int) -> None:
+    _check(load().geoloc_cnn_backward(cnn, dlogits_dev, batch, stream), "geoloc_cnn_backward")
+
+
+def geoloc_cnn_adam_step(cnn: int, lr: float, beta1: float, beta2: float, eps: float, stream: int) -> None:
+    _check(load().geoloc_cnn_adam_step(cnn, lr, beta1, beta2, eps, stream), "geoloc_cnn_adam_step")
+
+
+def geoloc_cnn_topk(cnn: int, logits_dev: int, batch: int, k: int, stream: int) -> Tuple[np.ndarray, np.ndarray]:
+    tiles = np.empty((batch, k), dtype=np.int32)
+    probs = np.empty((batch, k), dtype=np.float32)
+    _check(load().geoloc_cnn_topk(cnn, logits_dev, batch, k, tiles.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  probs.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream), "geoloc_cnn_topk")
+    return tiles, probs
+
+
+def geoloc_cnn_destroy(cnn: int) -> None:
+    _check(load().geoloc_cnn_destroy(cnn), "geoloc_cnn_destroy")
+
+
+class CNN:
+    """Tile-proposal network on the device; tensors are torch CUDA float32 NCHW."""
+
+    def __init__(self, in_ch: int = 3, hidden: int = 32, layers: int = 4, height: int = 64, width: int = 64,
+                 max_batch: int = 64):
+        d = geoloc_cnn_desc(in_ch, hidden, layers, height, width, max_batch)
+        self.in_ch, self.hidden, self.layers, self.height, self.width, self.max_batch = (
+            in_ch, hidden, layers, height, width, max_batch)
+        self.handle = geoloc_cnn_create(d)
+        self.n_params = geoloc_cnn_param_count(self.handle)
+
+    def set_params(self, theta: np.ndarray) -> None:
+        geoloc_cnn_set_params(self.handle, theta)
+
+    def params(self, which: int = 0) -> np.ndarray:
+        return geoloc_cnn_get_params(self.handle, which, self.n_params)
+
+    def prepare(self, J, D, nu, stream=None):
+        import torch
+        B = J.shape[0]
+        x = torch.empty((B, 3, self.height, self.width), dtype=torch.float32, device=J.device)
+        geoloc_cnn_prepare(self.handle, J.data_ptr(), D.data_ptr(), nu.data_ptr(), B, x.data_ptr(),
+                           _stream_handle(stream))
+        return x
+
+    def forward(self, x, stream=None):
+        import torch
+        B = x.shape[0]
+        z = torch.empty((B, self.height, self.width), dtype=torch.float32, device=x.device)
+        geoloc_cnn_forward(self.handle, x.data_ptr(), B, z.data_ptr(), _stream_handle(stream))
+        return z
+
+    def loss(self, z, label, stream=None):
+        import torch
+        B = z.shape[0]
+        dz = torch.empty_like(z)
+        loss = torch.empty(B, dtype=torch.float32, device=z.device)
+        geoloc_cnn_loss(self.handle, z.data_ptr(), label.data_ptr(), B, dz.data_ptr(), loss.data_ptr(),
+                        _stream_handle(stream))
+        return loss, dz
+
+    def backward(self, dz, stream=None) -> None:
+        geoloc_cnn_backward(self.handle, dz.data_ptr(), dz.shape[0], _stream_handle(stream))
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+        geoloc_cnn_adam_step(self.handle, lr, beta1, beta2, eps, _stream_handle(stream))
+
+    def topk(self, z, k: int, stream=None):
+        return geoloc_cnn_topk(self.handle, z.data_ptr(), z.shape[0], k, _stream_handle(stream))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            geoloc_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,362 @@
+"""Learned tile proposal over the direct position-domain map.
+
+This is an addition to the method (the paper has no learned part). Pipeline for one
+scenario, every step through libgeoloc on the GPU:
+  1. coarse map: the plain direct map at the centres of the 64 x 64 tiles (16 x 16
+     fine cells each) of the fine grid;
+  2. features [log-compressed coarse map, TDOA and FDOA of the middle step] -> CNN ->
+     tile logits -> softmax -> the 16 most likely tiles;
+  3. refine: the plain direct map at the 16 x 256 fine cells of those tiles, argmax;
+  4. fallback: when the softmax mass of the chosen tiles is below 0.5 (or, with
+     rule="top1", the top tile's probability), the plain map over the full grid.
+Training labels come from the plain full-grid map: every tile holding a cell within
+1 % of the map's maximum (orbital-plane mirror ties and flat ridges make it a set),
+uniformly weighted. Network: 4 convolutions 3 -> 32 -> 32 -> 32 -> 1, FP16 weights,
+FP32 accumulation, trained with Adam by the library's own kernels; PyTorch only holds
+the device buffers.
+
+CLI:  python -m paper_2508_06672_amd.proposal train --n-train 4000 --out <weights.npz>
+      python -m paper_2508_06672_amd.proposal evaluate --weights <weights.npz> --n-test 200
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import configs, sim
+
+COARSE = configs.PROPOSAL_COARSE
+TILE = configs.PROPOSAL_TILE
+TOPK = configs.PROPOSAL_TOPK
+LABEL_EPS = 1e-2
+IN_CH, HIDDEN, LAYERS = 3, 32, 4
+TRAIN_WL = configs.PROPOSAL.with_(name="proposal_train_1024x1024_10MHz_1e5", n_samples=100_000)
+SEED_TRAIN, SEED_VAL, SEED_TEST = 1_000_000, 1_020_000, 1_030_000
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal_cnn.npz")
+
+
+def log(msg: str) -> None:
+    print(f"[proposal {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------- grid helpers
+
+def coarse_axes(lat: np.ndarray, lon: np.ndarray, tile: int = TILE):
+    """Latitudes / longitudes of the tile centres of a rectilinear fine grid."""
+    def centres(a):
+        n = a.size // tile
+        i0 = tile * np.arange(n) + tile // 2 - 1
+        return 0.5 * (a[i0] + a[i0 + 1])
+    return centres(np.asarray(lat)), centres(np.asarray(lon))
+
+
+def tile_points(lat: np.ndarray, lon: np.ndarray, tiles: Sequence[int], tile: int = TILE):
+    """Fine-grid points (lat, lon, flat index) of the given tiles, tile by tile."""
+    n_tile_cols = lon.size // tile
+    idx = []
+    for t in tiles:
+        R, C = divmod(int(t), n_tile_cols)
+        rr, cc = np.meshgrid(np.arange(R * tile, (R + 1) * tile), np.arange(C * tile, (C + 1) * tile), indexing="ij")
+        idx.append((rr * lon.size + cc).ravel())
+    idx = np.concatenate(idx)
+    return lat[idx // lon.size], lon[idx % lon.size], idx
+
+
+def tile_label(J: np.ndarray, n_rows: int, n_cols: int, tile: int = TILE, eps: float = LABEL_EPS) -> np.ndarray:
+    """Uniform distribution over the tiles holding a cell with J >= (1 - eps) max J."""
+    Jt = np.asarray(J, dtype=np.float64).reshape(n_rows // tile, tile, n_cols // tile, tile).max(axis=(1, 3))
+    mask = Jt >= (1.0 - eps) * Jt.max()
+    return (mask / mask.sum()).ravel().astype(np.float32)
+
+
+def he_init(seed: int) -> np.ndarray:
+    """He-normal convolution weights, zero biases, in the library's flat parameter order."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    chans = [IN_CH] + [HIDDEN] * (LAYERS - 1) + [1]
+    out = []
+    for ci, co in zip(chans[:-1], chans[1:]):
+        out += [rng.standard_normal(co * ci * 9) * math.sqrt(2.0 / (ci * 9)), np.zeros(co)]
+    return np.concatenate(out).astype(np.float32)
+
+
+def save_weights(path: str, theta: np.ndarray, meta: dict) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, theta=np.asarray(theta, dtype=np.float32), meta=np.frombuffer(json.dumps(meta).encode(), np.uint8))
+
+
+def load_weights(path: str = WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return z["theta"], json.loads(bytes(z["meta"]).decode())
+
+
+# --------------------------------------------------------------------------- the proposer
+
+class Proposer:
+    """Plans and network for one fine-grid shape; set_grid() retargets a scenario."""
+
+    def __init__(self, wl, net, topk: int = TOPK, threshold: float = 0.5, rule: str = "mass"):
+        from . import geoloc
+        self.G = geoloc
+        self.wl, self.net, self.topk, self.threshold, self.rule = wl, net, topk, threshold, rule
+        lat0, lon0 = sim.make_grid(wl, 0.0)
+        clat, clon = coarse_axes(lat0, lon0)
+        kw = dict(n_rx=wl.n_rx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                  pairs=list(wl.pairs), earth_radius_m=wl.earth_radius_m)
+        self.coarse = geoloc.Plan(lat=clat, lon=clon, **kw)
+        plat, plon, _ = tile_points(lat0, lon0, range(topk))
+        self.refine = geoloc.Plan(lat=plat, lon=plon, grid_kind=geoloc.GRID_POINTS, **kw)
+        self.full = geoloc.Plan(lat=lat0, lon=lon0, **kw)
+        self.lat, self.lon = lat0, lon0
+        self.n_tile_rows, self.n_tile_cols = wl.n_rows // TILE, wl.n_cols // TILE
+
+    def set_grid(self, lat: np.ndarray, lon: np.ndarray) -> None:
+        self.lat, self.lon = np.asarray(lat), np.asarray(lon)
+        self.coarse.set_grid(*coarse_axes(lat, lon))
+        self.full.set_grid(lat, lon)
+
+    def coarse_features(self, caps, states):
+        """(coarse map [64*64], CNN input [1, 3, 64, 64])."""
+        Jc = self.coarse.map(caps, states)
+        D, nu = self.coarse.geometry(states, 0, self.wl.n_steps // 2, 1)
+        x = self.net.prepare(Jc.view(1, -1), D, nu)
+        return Jc, x
+
+    def refine_tiles(self, caps, states, tiles):
+        plat, plon, idx = tile_points(self.lat, self.lon, tiles)
+        self.refine.set_grid(plat, plon)
+        J = self.refine.map(caps, states)
+        i, v = self.refine.argmax(J)
+        return int(idx[int(i[0])]), float(v[0])
+
+    def full_map(self, caps, states):
+        J = self.full.map(caps, states)
+        i, v = self.full.argmax(J)
+        return int(i[0]), float(v[0]), J
+
+    def run(self, caps, states, selector: str = "cnn") -> Dict:
+        """selector: 'cnn' (learned) or 'coarse' (ablation: top tiles of the coarse map itself)."""
+        import torch
+        Jc, x = self.coarse_features(caps, states)
+        if selector == "cnn":
+            z = self.net.forward(x)
+            tiles, probs = self.net.topk(z, self.topk)
+            tiles, probs = tiles[0], probs[0]
+            score = float(probs[0]) if self.rule == "top1" else float(probs.sum())
+        else:
+            jc = Jc.cpu().numpy()
+            tiles = np.argsort(-jc, kind="stable")[: self.topk]
+            score, probs = 1.0, np.zeros(self.topk, dtype=np.float32)
+        if score < self.threshold:
+            i, v, _ = self.full_map(caps, states)
+            return {"idx": i, "val": v, "fallback": True, "tiles": tiles, "score": score}
+        i, v = self.refine_tiles(caps, states, tiles)
+        return {"idx": i, "val": v, "fallback": False, "tiles": tiles, "score": score}
+
+    def close(self) -> None:
+        for p in (self.coarse, self.refine, self.full):
+            p.close()
+
+
+# --------------------------------------------------------------------------- data
+
+def _simulate(args):
+    wl, seed = args
+    s = sim.make_scenario(wl, seed)
+    return seed, s.lat, s.lon, s.states, s.captures, s.emitters[0].waveform, s.snr_db
+
+
+def scenario_stream(wl, seeds: Sequence[int], pool=None):
+    """Simulated scenarios in seed order: in CPU worker processes (a pool forked before the
+    GPU was touched), or in this process when pool is None."""
+    jobs = [(wl, s) for s in seeds]
+    it = pool.imap(_simulate, jobs, chunksize=4) if pool is not None else map(_simulate, jobs)
+    for rec in it:
+        yield rec
+
+
+def build_dataset(prop: Proposer, wl, seeds, pool):
+    """Features [n, 3, 64, 64] and labels [n, 4096] on the GPU."""
+    import torch
+    n = len(seeds)
+    X = torch.empty((n, IN_CH, prop.n_tile_rows, prop.n_tile_cols), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, prop.n_tile_rows * prop.n_tile_cols), dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    for k, (seed, lat, lon, states, capn, wf, snr) in enumerate(scenario_stream(wl, seeds, pool)):
+        caps = torch.from_numpy(capn).cuda()
+        prop.set_grid(lat, lon)
+        _, x = prop.coarse_features(caps, states)
+        X[k] = x[0]
+        _, _, J = prop.full_map(caps, states)
+        Y[k] = torch.from_numpy(tile_label(J.cpu().numpy(), wl.n_rows, wl.n_cols)).cuda()
+        if (k + 1) % 250 == 0 or k + 1 == n:
+            log(f"  dataset {k + 1}/{n} ({time.time() - t0:.0f} s)")
+    return X, Y
+
+
+def train(net, X, Y, Xv, Yv, epochs: int, batch: int = 64, lr: float = 1e-3, seed: int = 0) -> List[dict]:
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = X.shape[0]
+    hist = []
+    step = 0
+    total = epochs * (n // batch)
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        tl = 0.0
+        for b in range(n // batch):
+            sel = perm[b * batch:(b + 1) * batch]
+            z = net.forward(X[sel])
+            loss, dz = net.loss(z, Y[sel])
+            net.backward(dz)
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / total))
+            net.adam_step(lr_t)
+            tl += float(loss.sum())
+            step += 1
+        vl, vh = validate(net, Xv, Yv)
+        hist.append({"epoch": ep, "train_loss": tl / (n // batch * batch), "val_loss": vl, "val_top16_hit": vh})
+        log(f"  epoch {ep}: train {hist[-1]['train_loss']:.4f} val {vl:.4f} top-16 hit {vh:.3f}")
+    return hist
+
+
+def validate(net, Xv, Yv, batch: int = 64):
+    import torch
+    n = Xv.shape[0]
+    tl, hit = 0.0, 0
+    for b in range(0, n, batch):
+        x, y = Xv[b:b + batch], Yv[b:b + batch]
+        z = net.forward(x)
+        loss, _ = net.loss(z, y)
+        tl += float(loss.sum())
+        tiles, _ = net.topk(z, TOPK)
+        yh = y.cpu().numpy()
+        hit += sum(bool(np.any(yh[i, tiles[i]] > 0)) for i in range(tiles.shape[0]))
+    return tl / n, hit / n
+
+
+# --------------------------------------------------------------------------- evaluation
+
+def _cell_dist(a: int, b: int, n_cols: int) -> int:
+    ra, ca = divmod(int(a), n_cols)
+    rb, cb = divmod(int(b), n_cols)
+    return max(abs(ra - rb), abs(ca - cb))
+
+
+def _agrees(wl, lat, lon, a: int, a_full: int, J_full: np.ndarray, tol: float = 1e-4) -> bool:
+    """Within one cell of the full map's peak or of its orbital-plane mirror (an exact tie),
+    or tol-optimal on the full map."""
+    r, c = divmod(a_full, wl.n_cols)
+    mr, mc = sim.nearest_cell(lat, lon, *sim.mirror_latlon(wl, lat[r], lon[c]))
+    m = mr * wl.n_cols + mc
+    if min(_cell_dist(a, a_full, wl.n_cols), _cell_dist(a, m, wl.n_cols)) <= 1:
+        return True
+    return bool(J_full[a] >= (1 - 2 * tol) * J_full[a_full])
+
+
+def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
+    import torch
+    recs = []
+    for seed, lat, lon, states, capn, wf, snr in scenario_stream(wl, seeds, pool):
+        caps = torch.from_numpy(capn).cuda()
+        prop.set_grid(lat, lon)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a_full, _, J = prop.full_map(caps, states)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t0
+        Jh = J.cpu().numpy()
+        out = {"seed": seed, "waveform": wf, "snr_db": snr, "t_full_ms": t_full * 1e3}
+        for sel in ("cnn", "coarse"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = prop.run(caps, states, selector=sel)
+            torch.cuda.synchronize()
+            out[sel] = {"ok": _agrees(wl, lat, lon, r["idx"], a_full, Jh), "fallback": r["fallback"],
+                        "score": r["score"], "t_ms": (time.perf_counter() - t0) * 1e3}
+        recs.append(out)
+        log(f"  seed {seed} {wf:5s} {snr:6.1f} dB: cnn ok={out['cnn']['ok']} fb={out['cnn']['fallback']} "
+            f"score={out['cnn']['score']:.2f} | coarse ok={out['coarse']['ok']}")
+    n = len(recs)
+
+    def summ(sel):
+        ok = [r[sel]["ok"] for r in recs]
+        fb = [r[sel]["fallback"] for r in recs]
+        t = [r[sel]["t_ms"] for r in recs]
+        return {"agree_rate": float(np.mean(ok)), "fallback_rate": float(np.mean(fb)),
+                "median_ms": float(np.median(t)), "speedup_vs_full_median": float(np.median(
+                    [r["t_full_ms"] / r[sel]["t_ms"] for r in recs]))}
+    return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "workload": wl.name,
+            "full_map_median_ms": float(np.median([r["t_full_ms"] for r in recs])),
+            "learned": summ("cnn"), "coarse_top16_ablation": summ("coarse"), "records": recs}
+
+
+# --------------------------------------------------------------------------- CLI
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--n-train", type=int, default=4000)
+    t.add_argument("--n-val", type=int, default=200)
+    t.add_argument("--epochs", type=int, default=12)
+    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--workers", type=int, default=16)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--n-test", type=int, default=200)
+    e.add_argument("--samples", type=int, default=configs.PROPOSAL.n_samples)
+    e.add_argument("--workers", type=int, default=16)
+    e.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+
+    # simulator workers are forked before anything touches the GPU
+    pool = mp.get_context("fork").Pool(args.workers)
+    import torch
+    from . import geoloc
+    assert torch.cuda.is_available()
+    net = geoloc.CNN(IN_CH, HIDDEN, LAYERS, COARSE, COARSE, max_batch=64)
+    try:
+        if args.cmd == "train":
+            wl = TRAIN_WL
+            prop = Proposer(wl, net)
+            log(f"building {args.n_train} training + {args.n_val} validation scenarios ({wl.name})")
+            X, Y = build_dataset(prop, wl, list(range(SEED_TRAIN, SEED_TRAIN + args.n_train)), pool)
+            Xv, Yv = build_dataset(prop, wl, list(range(SEED_VAL, SEED_VAL + args.n_val)), pool)
+            net.set_params(he_init(0))
+            hist = train(net, X, Y, Xv, Yv, args.epochs, lr=args.lr)
+            meta = {"in_ch": IN_CH, "hidden": HIDDEN, "layers": LAYERS, "n_params": net.n_params,
+                    "train_workload": wl.name, "n_train": args.n_train, "n_val": args.n_val,
+                    "seeds_train": [SEED_TRAIN, SEED_TRAIN + args.n_train], "epochs": args.epochs, "lr": args.lr,
+                    "label_eps": LABEL_EPS, "history": hist}
+            save_weights(args.out, net.params(0), meta)
+            log(f"saved {args.out} ({net.n_params} parameters)")
+            prop.close()
+        else:
+            theta, meta = load_weights(args.weights)
+            net.set_params(theta)
+            wl = configs.PROPOSAL.with_(n_samples=args.samples)
+            prop = Proposer(wl, net)
+            res = evaluate(prop, wl, list(range(SEED_TEST, SEED_TEST + args.n_test)), pool)
+            res["weights"] = os.path.basename(args.weights)
+            summary = {k: v for k, v in res.items() if k != "records"}
+            print(json.dumps(summary), flush=True)
+            if args.out:
+                with open(args.out, "w") as fh:
+                    json.dump(res, fh)
+            prop.close()
+    finally:
+        pool.terminate()
+        net.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

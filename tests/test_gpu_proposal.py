@@ -1,0 +1,89 @@
+"""The learned-proposal pipeline on the GPU: refine/fallback plumbing on a small grid,
+and (when trained weights are present) what the trained network gains over choosing
+tiles from the coarse map alone."""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import log, require_gpu
+from paper_2508_06672_amd import configs, sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2508_06672_amd import geoloc, proposal
+    geoloc.load()
+    return proposal
+
+
+SMALL_WL = configs.PROPOSAL.with_(name="proposal_small", n_rows=128, n_cols=160, n_samples=40_000,
+                                  waveform="chirp")
+
+
+def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
+    from paper_2508_06672_amd import geoloc
+    wl = SMALL_WL
+    net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
+    prop = P.Proposer(wl, net)
+    scn = sim.make_scenario(wl, 1)
+    caps = torch.from_numpy(scn.captures).cuda()
+    prop.set_grid(scn.lat, scn.lon)
+    r = prop.run(caps, scn.states)
+    a_full, v_full, _ = prop.full_map(caps, scn.states)
+    assert r["fallback"] and abs(r["score"] - P.TOPK / (8 * 10)) < 1e-5
+    assert r["idx"] == a_full and r["val"] == v_full
+    prop.close()
+    net.close()
+
+
+def test_refined_tiles_reproduce_the_full_map(torch, P):
+    """The refine map at the chosen tiles' cells equals the full map at those cells, and
+    when the chosen tiles contain the full map's peak the refined peak is that peak."""
+    from paper_2508_06672_amd import geoloc
+    wl = SMALL_WL
+    net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
+    prop = P.Proposer(wl, net)
+    scn = sim.make_scenario(wl, 2)
+    caps = torch.from_numpy(scn.captures).cuda()
+    prop.set_grid(scn.lat, scn.lon)
+    a_full, v_full, Jf = prop.full_map(caps, scn.states)
+    Jf = Jf.cpu().numpy()
+    tile_of = (a_full // wl.n_cols // P.TILE) * (wl.n_cols // P.TILE) + (a_full % wl.n_cols) // P.TILE
+    tiles = [tile_of] + [t for t in range(P.TOPK) if t != tile_of][: P.TOPK - 1]
+    plat, plon, idx = P.tile_points(scn.lat, scn.lon, tiles)
+    prop.refine.set_grid(plat, plon)
+    Jr = prop.refine.map(caps, scn.states).cpu().numpy()
+    assert np.array_equal(Jr, Jf[idx])
+    i, v = prop.refine_tiles(caps, scn.states, tiles)
+    assert i == a_full and v == v_full
+    prop.close()
+    net.close()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                                    "paper_2508_06672_amd", "weights", "proposal_cnn.npz")),
+                    reason="no trained proposal weights in the tree")
+def test_trained_network_beats_coarse_map_tiles(torch, P):
+    """On held-out seeds the trained network's tiles contain the full map's peak (or a
+    tie of it) at least as often as the 16 best tiles of the coarse map itself."""
+    from paper_2508_06672_amd import geoloc
+    theta, meta = P.load_weights()
+    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=64)
+    net.set_params(theta)
+    wl = P.TRAIN_WL
+    prop = P.Proposer(wl, net, threshold=0.0)           # no fallback: measure the tile choice itself
+    seeds = list(range(P.SEED_TEST, P.SEED_TEST + 24))
+    res = P.evaluate(prop, wl, seeds, None)
+    log(f"learned {res['learned']} ablation {res['coarse_top16_ablation']}")
+    assert res["learned"]["agree_rate"] >= res["coarse_top16_ablation"]["agree_rate"]
+    assert res["learned"]["agree_rate"] >= 0.8
+    prop.close()
+    net.close()
