@@ -62,6 +62,8 @@ struct geoloc_plan_s {
     int2* d_pairs = nullptr;
     double* d_D = nullptr;
     double* d_nu = nullptr;
+    double* d_partial = nullptr;     // [step groups][P] when a plan's grid is too small to fill the GPU
+    int32_t n_groups = 1;
     ArgmaxScratch am;
     int64_t device_bytes = 0;
     // host staging for receiver states (pinned) and its reuse guard
@@ -135,6 +137,7 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->d_pairs);
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_nu);
+    (void)hipFree(p->d_partial);
     (void)hipFree(p->am.part_val);
     (void)hipFree(p->am.part_idx);
     (void)hipFree(p->am.found_idx);
@@ -597,6 +600,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
         if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
+        p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, p->kc);
+        if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
         p->am.n_blocks = argmax_blocks(P);
         if ((rc = dev_alloc(p, &p->am.part_val, p->am.n_blocks))) break;
         if ((rc = dev_alloc(p, &p->am.part_idx, p->am.n_blocks))) break;
@@ -702,6 +707,8 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.inv_fs = 1.0 / p->fs;
         a.accum_mode = p->accum_mode;
         a.load_J = (k0 > 0) || (flags & GEOLOC_ACCUMULATE);
+        a.n_groups = std::min<int32_t>(p->n_groups, kc);
+        a.partial = p->d_partial;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
         HIP_TRY(launch_direct(a, p->delay_mode, s));
         if ((rc = span_end(p, s, &sc))) return rc;

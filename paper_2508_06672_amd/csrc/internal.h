@@ -45,7 +45,12 @@ struct DirectArgs {
     double inv_fs;
     int32_t accum_mode;
     int32_t load_J;          // add onto the existing J values
+    int32_t n_groups;        // step groups per chunk (1: each workgroup owns its points' J)
+    double* partial;         // [n_groups][P] partial sums when n_groups > 1
 };
+
+constexpr int32_t kMaxStepGroups = 64;
+int32_t direct_groups(int64_t n_tiles, int32_t kc);
 
 struct GeomArgs {
     const double* xyz;       // [P][3]

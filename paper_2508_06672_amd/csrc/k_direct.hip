@@ -44,7 +44,7 @@ namespace geoloc {
 
 constexpr int kR = GEOLOC_DIRECT_R;   // samples per phasor block
 constexpr int kT = GEOLOC_DIRECT_T;   // samples per LDS tile (multiple of kR)
-constexpr int kHalo = 512;            // largest lag spread of a tile staged in LDS
+constexpr int kHalo = 2048;           // largest lag spread of a tile staged in LDS
 static_assert(kT % kR == 0, "LDS tile must hold whole phasor blocks");
 
 // exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
@@ -137,18 +137,24 @@ void k_direct(DirectArgs a) {
     __shared__ int s_mm[2][4];
 
     const int tid = threadIdx.x;
+    // workgroup -> (point tile, step group): with n_groups > 1 each group sums its share of
+    // the chunk's steps into its own partial row, reduced afterwards in a fixed order
+    const int64_t tile = blockIdx.x % a.n_tiles;
+    const int group = (int)(blockIdx.x / a.n_tiles);
+    const int kk_lo = (int)((int64_t)a.kc * group / a.n_groups);
+    const int kk_hi = (int)((int64_t)a.kc * (group + 1) / a.n_groups);
     bool valid;
-    const int64_t p = tile_point(a.tiling, blockIdx.x, tid, &valid);
-    double jacc = (valid && a.load_J) ? (double)a.J[p] : 0.0;
+    const int64_t p = tile_point(a.tiling, tile, tid, &valid);
+    double jacc = (valid && a.load_J && a.n_groups == 1) ? (double)a.J[p] : 0.0;
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int e = 0; e < a.n_pairs; ++e) {
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
-        for (int kk = 0; kk < a.kc; ++kk) {
+        for (int kk = kk_lo; kk < kk_hi; ++kk) {
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + blockIdx.x) * kTilePoints + tid;
+            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
             double D = valid ? a.D[gi] : 0.0;
             const double nu = valid ? a.nu[gi] : 0.0;
             // keep the integer lag representable whatever the geometry (NaN included);
@@ -211,16 +217,41 @@ void k_direct(DirectArgs a) {
             jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
         }
     }
-    if (valid) a.J[p] = (float)jacc;
+    if (!valid) return;
+    if (a.n_groups == 1)
+        a.J[p] = (float)jacc;
+    else
+        a.partial[(int64_t)group * a.P + p] = jacc;
+}
+
+// J[p] = (J[p] if loading) + sum over step groups of the partial sums, in group order.
+__global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict__ partial, int32_t n_groups, int64_t P,
+                                                       int32_t load_J, float* __restrict__ J) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    double acc = load_J ? (double)J[p] : 0.0;
+    for (int g = 0; g < n_groups; ++g) acc += partial[(int64_t)g * P + p];
+    J[p] = (float)acc;
+}
+
+int32_t direct_groups(int64_t n_tiles, int32_t kc) {
+    // enough workgroups to cover 256 CUs several times over
+    int64_t g = (1024 + n_tiles - 1) / n_tiles;
+    if (g > kc) g = kc;
+    if (g > kMaxStepGroups) g = kMaxStepGroups;
+    return (int32_t)(g < 1 ? 1 : g);
 }
 
 hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s) {
-    const int64_t tiles = a.tiling.tiles_x * a.tiling.tiles_y;
-    dim3 grid((unsigned)tiles), block(256);
+    dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
         hipLaunchKernelGGL(k_direct<true>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(k_direct<false>, grid, block, 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n_groups == 1) return e;
+    hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((a.P + 255) / 256)), block, 0, s, (const double*)a.partial,
+                       a.n_groups, a.P, a.load_J, a.J);
     return hipGetLastError();
 }
 

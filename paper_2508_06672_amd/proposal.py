@@ -226,19 +226,41 @@ def train(net, X, Y, Xv, Yv, epochs: int, batch: int = 64, lr: float = 1e-3, see
     return hist
 
 
-def validate(net, Xv, Yv, batch: int = 64):
+def validate(net, Xv, Yv, batch: int = 64, scores: bool = False):
+    """Mean loss and the fraction of samples whose top tiles hit the label set; with
+    scores=True also per-sample (top-tile mass, top-1 probability, hit)."""
     import torch
     n = Xv.shape[0]
-    tl, hit = 0.0, 0
+    tl, hits, rec = 0.0, 0, []
     for b in range(0, n, batch):
         x, y = Xv[b:b + batch], Yv[b:b + batch]
         z = net.forward(x)
         loss, _ = net.loss(z, y)
         tl += float(loss.sum())
-        tiles, _ = net.topk(z, TOPK)
+        tiles, probs = net.topk(z, TOPK)
         yh = y.cpu().numpy()
-        hit += sum(bool(np.any(yh[i, tiles[i]] > 0)) for i in range(tiles.shape[0]))
-    return tl / n, hit / n
+        for i in range(tiles.shape[0]):
+            h = bool(np.any(yh[i, tiles[i]] > 0))
+            hits += h
+            rec.append((float(probs[i].sum()), float(probs[i, 0]), h))
+    return (tl / n, hits / n, rec) if scores else (tl / n, hits / n)
+
+
+def calibrate(rec, target: float = 0.99, rule: str = "mass") -> dict:
+    """Smallest threshold on the confidence score whose accepted samples hit the label set
+    at rate >= target (the rest fall back to the full map)."""
+    sc = np.array([r[0] if rule == "mass" else r[1] for r in rec])
+    hit = np.array([r[2] for r in rec])
+    best = float(np.inf)
+    for t in np.unique(sc)[::-1]:
+        acc = sc >= t
+        if hit[acc].mean() >= target:
+            best = float(t)
+        else:
+            break
+    acc = sc >= best
+    return {"rule": rule, "threshold": best, "target": target, "accept_rate": float(acc.mean()),
+            "accepted_hit_rate": float(hit[acc].mean()) if acc.any() else None}
 
 
 # --------------------------------------------------------------------------- evaluation
@@ -303,9 +325,9 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--n-train", type=int, default=4000)
+    t.add_argument("--n-train", type=int, default=8000)
     t.add_argument("--n-val", type=int, default=200)
-    t.add_argument("--epochs", type=int, default=12)
+    t.add_argument("--epochs", type=int, default=20)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--workers", type=int, default=16)
     t.add_argument("--out", default=WEIGHTS)
@@ -315,6 +337,7 @@ def main(argv=None) -> int:
     e.add_argument("--samples", type=int, default=configs.PROPOSAL.n_samples)
     e.add_argument("--workers", type=int, default=16)
     e.add_argument("--out", default=None)
+    e.add_argument("--threshold", type=float, default=None, help="override the calibrated threshold")
     args = ap.parse_args(argv)
 
     # simulator workers are forked before anything touches the GPU
@@ -332,7 +355,11 @@ def main(argv=None) -> int:
             Xv, Yv = build_dataset(prop, wl, list(range(SEED_VAL, SEED_VAL + args.n_val)), pool)
             net.set_params(he_init(0))
             hist = train(net, X, Y, Xv, Yv, args.epochs, lr=args.lr)
+            _, _, rec = validate(net, Xv, Yv, scores=True)
+            cal = calibrate(rec)
+            log(f"calibration on the validation set: {cal}")
             meta = {"in_ch": IN_CH, "hidden": HIDDEN, "layers": LAYERS, "n_params": net.n_params,
+                    "calibration": cal, "threshold": cal["threshold"], "rule": cal["rule"],
                     "train_workload": wl.name, "n_train": args.n_train, "n_val": args.n_val,
                     "seeds_train": [SEED_TRAIN, SEED_TRAIN + args.n_train], "epochs": args.epochs, "lr": args.lr,
                     "label_eps": LABEL_EPS, "history": hist}
@@ -343,9 +370,12 @@ def main(argv=None) -> int:
             theta, meta = load_weights(args.weights)
             net.set_params(theta)
             wl = configs.PROPOSAL.with_(n_samples=args.samples)
-            prop = Proposer(wl, net)
+            thr = args.threshold if args.threshold is not None else meta.get("threshold", 0.5)
+            prop = Proposer(wl, net, threshold=thr, rule=meta.get("rule", "mass"))
+            log(f"threshold {thr} ({meta.get('rule', 'mass')})")
             res = evaluate(prop, wl, list(range(SEED_TEST, SEED_TEST + args.n_test)), pool)
             res["weights"] = os.path.basename(args.weights)
+            res["threshold"] = thr
             summary = {k: v for k, v in res.items() if k != "records"}
             print(json.dumps(summary), flush=True)
             if args.out:
