@@ -53,7 +53,10 @@ extern "C" {
 #define GEOLOC_ELAUNCH      -7   /* a HIP runtime call or kernel launch failed */
 
 /* method */
-#define GEOLOC_DIRECT_FP32   0   /* Eq. (11) evaluated per point in FP32 (FP64 geometry)  */
+#define GEOLOC_DIRECT_FP32   0   /* Eq. (11) in FP32 with FP64 geometry; on RECT grids the
+                                    per-point sums are factored through lag moments shared by
+                                    a 16 x 16 tile (Taylor remainder <= 1e-9 per block) */
+#define GEOLOC_DIRECT_FP32_POINTWISE 3  /* the same map, every point summed on its own      */
 #define GEOLOC_CAF_BF16      1   /* CAF table on MFMA, BF16 inputs, FP32 accumulate        */
 #define GEOLOC_CAF_FP16      2   /* CAF table on MFMA, FP16 inputs, FP32 accumulate        */
 
@@ -123,7 +126,9 @@ typedef struct geoloc_plan_info {
     int64_t correlate_launches;/* launches of the dominant correlation kernel            */
     double geometry_ms;        /* summed HIP-event times of the geometry kernels         */
     double correlate_ms;       /* ... of the correlation kernels (direct, or CAF GEMM)   */
-    double interp_ms;          /* ... of the CAF interpolation kernels (0 for direct)    */
+    double interp_ms;          /* ... of the CAF interpolation kernels; for the direct
+                                  method, of the per-point pass over (tile, step) pairs the
+                                  factored kernel left to it                              */
     double map_ms;             /* ... of whole geoloc_map calls, first to last kernel    */
 } geoloc_plan_info;
 

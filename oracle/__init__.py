@@ -52,6 +52,30 @@ def _load():
     return _lib
 
 
+class use_library:
+    """Context manager that points every oracle call at another build of geoloc_oracle.c
+    (used by the tests that plant mistakes in the oracle to show that the pins catch them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self._saved = _load()
+        _lib = None
+        saved_path = globals()["LIB_PATH"]
+        globals()["LIB_PATH"] = self.path
+        try:
+            _load()
+        finally:
+            globals()["LIB_PATH"] = saved_path
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+
+
 def _dptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <new>
@@ -64,6 +65,8 @@ struct geoloc_plan_s {
     double* d_nu = nullptr;
     double* d_partial = nullptr;     // [step groups][P] when a plan's grid is too small to fill the GPU
     int32_t n_groups = 1;
+    uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
+    bool use_fact = false;           // factored direct kernel (RECT grids large enough to fill the GPU)
     ArgmaxScratch am;
     int64_t device_bytes = 0;
     // host staging for receiver states (pinned) and its reuse guard
@@ -138,6 +141,7 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_nu);
     (void)hipFree(p->d_partial);
+    (void)hipFree(p->d_deferred);
     (void)hipFree(p->am.part_val);
     (void)hipFree(p->am.part_idx);
     (void)hipFree(p->am.found_idx);
@@ -502,7 +506,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     if (d->n_rows > (1ll << 31) || d->n_cols > (1ll << 31) || d->n_rows * d->n_cols > (1ll << 34))
         return fail(GEOLOC_EINVAL, "grid too large");
     if (!d->lat || !d->lon) return fail(GEOLOC_EINVAL, "NULL lat or lon");
-    if (d->method != GEOLOC_DIRECT_FP32 && d->method != GEOLOC_CAF_BF16 && d->method != GEOLOC_CAF_FP16)
+    if (d->method != GEOLOC_DIRECT_FP32 && d->method != GEOLOC_CAF_BF16 && d->method != GEOLOC_CAF_FP16 &&
+        d->method != GEOLOC_DIRECT_FP32_POINTWISE)
         return fail(GEOLOC_EINVAL, "unknown method %d", d->method);
     if (d->delay_mode != GEOLOC_DELAY_LINEAR && d->delay_mode != GEOLOC_DELAY_ROUND)
         return fail(GEOLOC_EINVAL, "unknown delay_mode %d", d->delay_mode);
@@ -530,7 +535,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if (!std::isfinite(d->lat[i])) return fail(GEOLOC_EINVAL, "lat[%lld] not finite", (long long)i);
     for (int64_t i = 0; i < n_lon; ++i)
         if (!std::isfinite(d->lon[i])) return fail(GEOLOC_EINVAL, "lon[%lld] not finite", (long long)i);
-    if (d->method != GEOLOC_DIRECT_FP32) {
+    const bool caf = d->method == GEOLOC_CAF_BF16 || d->method == GEOLOC_CAF_FP16;
+    if (caf) {
         if (d->caf_bins != 0 && (d->caf_bins < 4 || d->caf_bins > 65536))
             return fail(GEOLOC_EINVAL, "caf_bins must be 0 or in [4, 65536]");
         if (d->caf_lags < 0 || (d->caf_lags > 0 && d->caf_lags < 3) || d->caf_lags > (1 << 20))
@@ -602,6 +608,10 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
         p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, p->kc);
         if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
+        p->use_fact = p->method == GEOLOC_DIRECT_FP32 && p->grid_kind == GEOLOC_GRID_RECT;
+        if (p->use_fact &&
+            (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->tiling.tiles_x * p->tiling.tiles_y)))
+            break;
         p->am.n_blocks = argmax_blocks(P);
         if ((rc = dev_alloc(p, &p->am.part_val, p->am.n_blocks))) break;
         if ((rc = dev_alloc(p, &p->am.part_idx, p->am.n_blocks))) break;
@@ -677,7 +687,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
     if (rc) return rc;
     TimedSpan whole{};
     if ((rc = span_begin(p, s, &whole, 3))) return rc;
-    if (p->method != GEOLOC_DIRECT_FP32) {
+    if (p->method == GEOLOC_CAF_BF16 || p->method == GEOLOC_CAF_FP16) {
         if ((rc = caf_map(p, in, J, flags, s))) return rc;
         if ((rc = span_end(p, s, &whole))) return rc;
         if (p->timing) p->timed_maps++;
@@ -709,10 +719,25 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.load_J = (k0 > 0) || (flags & GEOLOC_ACCUMULATE);
         a.n_groups = std::min<int32_t>(p->n_groups, kc);
         a.partial = p->d_partial;
+        a.mask = nullptr;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
-        HIP_TRY(launch_direct(a, p->delay_mode, s));
+        if (p->use_fact)
+            HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, s));
+        else
+            HIP_TRY(launch_direct(a, p->delay_mode, s));
         if ((rc = span_end(p, s, &sc))) return rc;
         if (p->timing) p->correlate_launches++;
+        if (p->use_fact) {
+            // the per-point kernel adds the (tile, step) pairs the factored kernel deferred
+            TimedSpan sd{};
+            DirectArgs m = a;
+            m.mask = p->d_deferred;
+            m.load_J = 1;
+            if ((rc = span_begin(p, s, &sd, 2))) return rc;
+            HIP_TRY(launch_direct(m, p->delay_mode, s));
+            if ((rc = span_end(p, s, &sd))) return rc;
+        }
+        HIP_TRY(launch_direct_reduce(a, s));
     }
     if ((rc = span_end(p, s, &whole))) return rc;
     if (p->timing) p->timed_maps++;
@@ -736,7 +761,8 @@ int geoloc_geometry(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index
 int geoloc_caf_table(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo, int64_t n_steps,
                      void* T_dev, int64_t T_capacity) {
     if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
-    if (p->method == GEOLOC_DIRECT_FP32) return fail(GEOLOC_EINVAL, "geoloc_caf_table needs a CAF method");
+    if (p->method != GEOLOC_CAF_BF16 && p->method != GEOLOC_CAF_FP16)
+        return fail(GEOLOC_EINVAL, "geoloc_caf_table needs a CAF method");
     if (!in || !in->captures || !in->rx_state || !T_dev) return fail(GEOLOC_EINVAL, "NULL input or output");
     if (((uintptr_t)in->captures & 7) != 0 || ((uintptr_t)T_dev & 7) != 0)
         return fail(GEOLOC_EINVAL, "captures and T_dev must be 8-byte aligned");
@@ -803,7 +829,7 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.delay_mode = p->delay_mode;
     r.caf_lag_lo = (int32_t)p->caf_lag_lo;
     r.caf_lags = p->caf_n_lags;
-    r.caf_bins = p->method == GEOLOC_DIRECT_FP32 ? 0 : p->caf_bins;
+    r.caf_bins = (p->method == GEOLOC_CAF_BF16 || p->method == GEOLOC_CAF_FP16) ? p->caf_bins : 0;
     r.caf_nu_lo_hz = p->caf_nu_lo;
     r.caf_nu_hi_hz = p->caf_nu_hi;
     r.device_bytes = p->device_bytes;

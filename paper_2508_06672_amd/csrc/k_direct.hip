@@ -47,13 +47,6 @@ constexpr int kT = GEOLOC_DIRECT_T;   // samples per LDS tile (multiple of kR)
 constexpr int kHalo = 2048;           // largest lag spread of a tile staged in LDS
 static_assert(kT % kR == 0, "LDS tile must hold whole phasor blocks");
 
-// exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
-__device__ inline float2 cis_cycles(double cyc) {
-    double f = cyc - rint(cyc);
-    float s, c;
-    sincospif((float)(2.0 * f), &s, &c);
-    return make_float2(c, s);
-}
 
 __device__ inline void wg_minmax(int& lo, int& hi, int (*s_mm)[4]) {
 #pragma unroll
@@ -145,7 +138,10 @@ void k_direct(DirectArgs a) {
     const int kk_hi = (int)((int64_t)a.kc * (group + 1) / a.n_groups);
     bool valid;
     const int64_t p = tile_point(a.tiling, tile, tid, &valid);
-    double jacc = (valid && a.load_J && a.n_groups == 1) ? (double)a.J[p] : 0.0;
+    // step groups: a masked pass adds onto the partial sums the factored kernel wrote
+    double jacc = 0.0;
+    if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
+    if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int e = 0; e < a.n_pairs; ++e) {
@@ -153,6 +149,8 @@ void k_direct(DirectArgs a) {
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         for (int kk = kk_lo; kk < kk_hi; ++kk) {
+            // with a mask, only the (tile, step) pairs the factored kernel left over
+            if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
             const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
             double D = valid ? a.D[gi] : 0.0;
@@ -248,10 +246,13 @@ hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s)
         hipLaunchKernelGGL(k_direct<true>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(k_direct<false>, grid, block, 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.n_groups == 1) return e;
-    hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((a.P + 255) / 256)), block, 0, s, (const double*)a.partial,
-                       a.n_groups, a.P, a.load_J, a.J);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_reduce(const DirectArgs& a, hipStream_t s) {
+    if (a.n_groups == 1) return hipSuccess;
+    hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s,
+                       (const double*)a.partial, a.n_groups, a.P, a.load_J, a.J);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgeoloc.so")
 ABI_VERSION = 1
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
-DIRECT_FP32, CAF_BF16, CAF_FP16 = 0, 1, 2
+DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
 DELAY_LINEAR, DELAY_ROUND = 0, 1
 ACC_POWER, ACC_MAG = 0, 1
 GRID_RECT, GRID_POINTS = 0, 1

@@ -153,7 +153,7 @@ class Proposer:
         else:
             jc = Jc.cpu().numpy()
             tiles = np.argsort(-jc, kind="stable")[: self.topk]
-            score, probs = 1.0, np.zeros(self.topk, dtype=np.float32)
+            score = float("inf")                      # the ablation never falls back
         if score < self.threshold:
             i, v, _ = self.full_map(caps, states)
             return {"idx": i, "val": v, "fallback": True, "tiles": tiles, "score": score}
@@ -311,9 +311,14 @@ def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
         ok = [r[sel]["ok"] for r in recs]
         fb = [r[sel]["fallback"] for r in recs]
         t = [r[sel]["t_ms"] for r in recs]
+        by_wf = {}
+        for wf in sorted({r["waveform"] for r in recs}):
+            sub = [r for r in recs if r["waveform"] == wf]
+            by_wf[wf] = {"n": len(sub), "agree_rate": float(np.mean([r[sel]["ok"] for r in sub])),
+                         "fallback_rate": float(np.mean([r[sel]["fallback"] for r in sub]))}
         return {"agree_rate": float(np.mean(ok)), "fallback_rate": float(np.mean(fb)),
                 "median_ms": float(np.median(t)), "speedup_vs_full_median": float(np.median(
-                    [r["t_full_ms"] / r[sel]["t_ms"] for r in recs]))}
+                    [r["t_full_ms"] / r[sel]["t_ms"] for r in recs])), "by_waveform": by_wf}
     return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "workload": wl.name,
             "full_map_median_ms": float(np.median([r["t_full_ms"] for r in recs])),
             "learned": summ("cnn"), "coarse_top16_ablation": summ("coarse"), "records": recs}

@@ -175,3 +175,32 @@ def test_map_1e6_sampled_points(torch, G):
     assert e <= DIRECT_TOL
     # the peak of the sampled window is the GPU's peak within tolerance
     assert Jo[np.searchsorted(idx, ag)] >= (1 - 2 * DIRECT_TOL) * np.max(Jo)
+
+
+def test_factored_and_pointwise_kernels_agree_at_1e6(torch, G):
+    """The tile-factored kernel (default on RECT grids) and the per-point kernel compute
+    the same 1e6-point map to FP32 rounding."""
+    wl = configs.MAP_1E6
+    scn = sim.make_scenario(wl, 1)
+    log("1e6 map: factored vs pointwise")
+    Jf = _gpu_map(torch, G, scn)
+    Jp = _gpu_map(torch, G, scn, method=G.DIRECT_FP32_POINTWISE)
+    e = err_J(Jf, Jp)
+    log(f"  factored vs pointwise err_J = {e:.3g}")
+    assert e <= 2e-5
+    check_argmax(Jf, Jp, 2e-5)
+
+
+def test_factored_kernel_defers_wide_tiles(torch, G):
+    """8 km cells at 10 MHz: a 16 x 16 tile spans hundreds of lags, so the factored kernel
+    hands every step to the per-point kernel; a 0.5 km grid next to it is factored. Both
+    match the oracle, in LINEAR and ROUND delay."""
+    for spacing, name in ((8000.0, "wide"), (500.0, "narrow")):
+        wl = configs.MAP_1E6.with_(n_rows=37, n_cols=41, spacing_m=spacing, n_samples=30_000)
+        scn = sim.make_scenario(wl, 11)
+        for delay in (0, 1):
+            log(f"factored {name} delay={delay}")
+            Jo = oracle.map_scenario(scn, delay_mode=delay)
+            Jg = _gpu_map(torch, G, scn, delay_mode=delay)
+            assert err_J(Jg, Jo) <= DIRECT_TOL, (name, delay)
+            check_argmax(Jg, Jo, DIRECT_TOL)
