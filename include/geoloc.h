@@ -53,9 +53,13 @@ extern "C" {
 #define GEOLOC_ELAUNCH      -7   /* a HIP runtime call or kernel launch failed */
 
 /* method */
-#define GEOLOC_DIRECT_FP32   0   /* Eq. (11) in FP32 with FP64 geometry; on RECT grids the
-                                    per-point sums are factored through lag moments shared by
-                                    a 16 x 16 tile (Taylor remainder <= 1e-9 per block) */
+#define GEOLOC_DIRECT_FP32   0   /* Eq. (11) in FP32 with FP64 geometry; the per-point sums
+                                    are factored through lag moments shared by a tile of 256
+                                    points (16 x 16 cells on RECT grids, 256 consecutive
+                                    points on POINTS grids), with a Taylor remainder of at
+                                    most 2^-24 of each 64-sample block's magnitude sum;
+                                    tiles whose lags or Doppler shifts spread too widely are
+                                    summed point by point */
 #define GEOLOC_DIRECT_FP32_POINTWISE 3  /* the same map, every point summed on its own      */
 #define GEOLOC_CAF_BF16      1   /* CAF table on MFMA, BF16 inputs, FP32 accumulate        */
 #define GEOLOC_CAF_FP16      2   /* CAF table on MFMA, FP16 inputs, FP32 accumulate        */
@@ -201,6 +205,25 @@ int geoloc_destroy(geoloc_plan_t plan);
 
 const char* geoloc_strerror(int status);
 const char* geoloc_last_error(void);
+
+/* Sub-band split of complex captures (a DFT filter bank), the input of the learned tile
+ * proposal's coarse map. Not a step of the paper's method: a coarse grid evaluated at
+ * cell centres from full-band samples misses the one-sample-wide delay ridge of a
+ * wideband emitter, while the same map over M decimated bands (delay resolution M
+ * samples) summed over the bands does not, and a narrowband emitter stays in its band.
+ *   out[b][c][m] = sum_{t=-h}^{h} g[t] exp(+j 2 pi (b - M/2) t / M) x_c[m M - t],
+ * b = 0..M-1 (band centre (b - M/2) fs / M), m = 0..N/M-1, x_c = 0 outside [0, N);
+ * g[t] = g0[t] w[t] / sum_s g0[s] w[s] with g0[t] = sin(pi t / M) / (pi t) (1/M at 0) and
+ * the Blackman window w[t] = 0.42 + 0.5 cos(pi t / h) + 0.08 cos(2 pi t / h).
+ * captures: DEVICE complex64 [n_ch][n_samples]; out: DEVICE complex64
+ * [n_bands][n_ch][n_samples / n_bands], band-major, so that it reads as the captures of
+ * n_bands * n_ch receivers (band b of channel c = receiver b * n_ch + c). Both owned by
+ * the caller, 8-byte aligned, not overlapping. Asynchronous on `stream` (NULL = default).
+ * Errors: EINVAL (null or misaligned buffer, n_ch < 1, n_samples < 1, n_bands outside
+ * 1..32 or not dividing n_samples, half_taps outside 1..128, n_bands (2 half_taps + 1)
+ * above 4096), EDEVICE, ELAUNCH. */
+int geoloc_subbands(const void* captures, int32_t n_ch, int64_t n_samples, int32_t n_bands, int32_t half_taps,
+                    void* out, void* stream);
 
 /* ------------------------------------------------------------------------------------
  * Learned tile proposal. Not part of the paper: a small CNN reads a coarse map of the

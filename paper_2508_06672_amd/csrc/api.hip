@@ -66,7 +66,7 @@ struct geoloc_plan_s {
     double* d_partial = nullptr;     // [step groups][P] when a plan's grid is too small to fill the GPU
     int32_t n_groups = 1;
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
-    bool use_fact = false;           // factored direct kernel (RECT grids large enough to fill the GPU)
+    bool use_fact = false;           // factored direct kernel (method GEOLOC_DIRECT_FP32)
     ArgmaxScratch am;
     int64_t device_bytes = 0;
     // host staging for receiver states (pinned) and its reuse guard
@@ -608,7 +608,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
         p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, p->kc);
         if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
-        p->use_fact = p->method == GEOLOC_DIRECT_FP32 && p->grid_kind == GEOLOC_GRID_RECT;
+        p->use_fact = p->method == GEOLOC_DIRECT_FP32;
         if (p->use_fact &&
             (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->tiling.tiles_x * p->tiling.tiles_y)))
             break;
@@ -840,6 +840,48 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.interp_ms = p->t_interp;
     r.map_ms = p->t_map;
     *out = r;
+    return GEOLOC_OK;
+}
+
+int geoloc_subbands(const void* captures, int32_t n_ch, int64_t n_samples, int32_t n_bands, int32_t half_taps,
+                    void* out, void* stream) {
+    if (captures == nullptr || out == nullptr) return fail(GEOLOC_EINVAL, "geoloc_subbands: null buffer");
+    if ((reinterpret_cast<uintptr_t>(captures) & 7u) || (reinterpret_cast<uintptr_t>(out) & 7u))
+        return fail(GEOLOC_EINVAL, "geoloc_subbands: buffers must be 8-byte aligned");
+    if (n_ch < 1 || n_samples < 1) return fail(GEOLOC_EINVAL, "geoloc_subbands: empty input");
+    if (n_bands < 1 || n_bands > kSubbandMaxBands)
+        return fail(GEOLOC_EINVAL, "geoloc_subbands: n_bands %d outside 1..%d", n_bands, kSubbandMaxBands);
+    if (n_samples % n_bands)
+        return fail(GEOLOC_EINVAL, "geoloc_subbands: n_samples %lld not divisible by n_bands %d",
+                    (long long)n_samples, n_bands);
+    if (half_taps < 1 || half_taps > kSubbandMaxHalf)
+        return fail(GEOLOC_EINVAL, "geoloc_subbands: half_taps %d outside 1..%d", half_taps, kSubbandMaxHalf);
+    if ((int64_t)n_bands * (2 * half_taps + 1) > kSubbandMaxTable)
+        return fail(GEOLOC_EINVAL, "geoloc_subbands: n_bands x (2 half_taps + 1) exceeds %d", kSubbandMaxTable);
+    const int64_t n_seg = (n_samples / n_bands + 63) / 64;
+    if (n_seg * n_ch > (int64_t)INT32_MAX) return fail(GEOLOC_EINVAL, "geoloc_subbands: input too long");
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    SubbandArgs a{};
+    a.in = static_cast<const float2*>(captures);
+    a.out = static_cast<float2*>(out);
+    a.N = n_samples;
+    a.n_ch = n_ch;
+    a.n_bands = n_bands;
+    a.half_taps = half_taps;
+    // Blackman-windowed sinc, cut-off 1/(2M) cycles per sample, unit DC gain (FP64)
+    const double pi = 3.14159265358979323846;
+    double g[2 * kSubbandMaxHalf + 1];
+    double sum = 0.0;
+    for (int t = -half_taps; t <= half_taps; ++t) {
+        const double g0 = t == 0 ? 1.0 / n_bands : std::sin(pi * t / n_bands) / (pi * t);
+        const double w = 0.42 + 0.5 * std::cos(pi * t / half_taps) + 0.08 * std::cos(2.0 * pi * t / half_taps);
+        g[t + half_taps] = g0 * w;
+        sum += g0 * w;
+    }
+    for (int i = 0; i < 2 * half_taps + 1; ++i) a.taps[i] = (float)(g[i] / sum);
+    HIP_TRY(launch_subband(a, static_cast<hipStream_t>(stream)));
     return GEOLOC_OK;
 }
 

@@ -178,4 +178,17 @@ hipError_t launch_cnn_to_half(const float* src, _Float16* dst, int64_t n, hipStr
 hipError_t launch_cnn_topk(const float* z, int T, int B, int k, int32_t* tiles, float* probs, hipStream_t s);
 hipError_t launch_cnn_prep(const float* J, const double* D, const double* nu, int T, int B, float* x, hipStream_t s);
 
+// sub-band split (the proposal's coarse-map input)
+constexpr int kSubbandMaxBands = 32;
+constexpr int kSubbandMaxHalf = 128;
+constexpr int kSubbandMaxTable = 4096;   // bands x taps
+struct SubbandArgs {
+    const float2* in;        // [n_ch][N]
+    float2* out;             // [n_bands][n_ch][N / n_bands]
+    int64_t N;
+    int32_t n_ch, n_bands, half_taps;
+    float taps[2 * kSubbandMaxHalf + 1];   // low-pass g[-h..h]
+};
+hipError_t launch_subband(const SubbandArgs& a, hipStream_t s);
+
 }  // namespace geoloc

@@ -15,12 +15,14 @@
 //   a_q(p) = (j delta_p)^q / q!,   G_q(b, d) = sum_{r in b} r^q x[n] e^{j theta_bar r} conj(y_j[n + d]).
 //
 // The moments G_q(b, d) depend on the lag only, not on the point, so a tile computes them
-// once for its few dozen lags (lanes over lags, 64 samples each) and every point combines
-// 2Q of them per block: about 3 VALU instructions per grid-point x sample correlation
-// instead of 13 for the per-point form. Q is chosen per tile and step so that the Taylor
-// remainder is below 1e-9 of the block sum (far under FP32 rounding); a tile whose lag
-// spread exceeds kFH or whose Doppler spread needs more than kFQ terms is flagged in
-// `deferred` and left to the per-point kernel, which then adds that step into J.
+// once for its few dozen lags and every point combines 2Q of them per block: about 2 VALU
+// instructions per grid-point x sample correlation instead of 13 for the per-point form.
+// The moment work is spread over the workgroup as (block, lag) items, floor(256 / H) blocks
+// of H lags per round, so that few lanes idle whatever the tile's lag spread H. Q is chosen
+// per tile and step so that the Taylor remainder bound is at most one FP32 unit roundoff
+// (2^-24) of the block's magnitude sum, below the rounding of the block sum itself; a tile
+// whose lag spread exceeds kFH or whose Doppler spread needs more than kFQ terms is flagged
+// in `deferred` and left to the per-point kernel, which then adds that step into J.
 #include "internal.h"
 
 #include <cfloat>
@@ -29,10 +31,11 @@
 namespace geoloc {
 
 constexpr int kFB = 64;          // samples per moment block
-constexpr int kFT = 1024;        // samples per LDS tile (16 blocks)
+constexpr int kFTB = 16;         // most blocks per LDS tile
+constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
 constexpr int kFQ = 4;           // most Taylor terms
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
-constexpr float kFTol = 1e-9f;   // Taylor remainder bound (relative)
+constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
 
 // Workgroup min / max of two ints and two floats (wave shuffles, then LDS).
 __device__ inline void wg_extent(int& dlo, int& dhi, float& tlo, float& thi, int (*si)[4], float (*sf)[4]) {
@@ -93,12 +96,12 @@ template <bool kRound>
 __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     __shared__ float2 s_y[kFT + kFH + 2];
     __shared__ float2 s_v[kFT];
-    __shared__ float2 s_G[4][kFQ][kFH];
+    __shared__ float2 s_G[kFQ * 256];          // [round block][q][lag], at most 256 (block, lag) items
     __shared__ float2 s_rot[kFB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     // workgroup -> (point tile, step group), as in the per-point kernel
     const int64_t tile = blockIdx.x % a.n_tiles;
     const int group = (int)(blockIdx.x / a.n_tiles);
@@ -155,14 +158,14 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
             if (!fact) continue;                           // uniform: the per-point kernel takes it
 
             const int H = (int)spread + 2;
+            const int NB = min(kFTB, 256 / H);            // blocks per round
+            const int TB = NB * (kFTB / NB);              // blocks per LDS tile (whole rounds)
+            const int my_b = tid / H;                     // this thread's (block, lag) item
+            const int my_l = tid - my_b * H;
             const int off = valid ? d0 - dlo : 0;
-            // a_q = (j delta)^q / q!
+            // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
             const float dl = (float)(two_pi * cyc - (double)tbar);
-            float2 aq[kFQ];
-            aq[0] = make_float2(1.f, 0.f);
-            aq[1] = make_float2(0.f, dl);
-            aq[2] = make_float2(-0.5f * dl * dl, 0.f);
-            aq[3] = make_float2(0.f, -dl * dl * dl * (1.f / 6.f));
+            const float c1 = dl, c2 = -0.5f * dl * dl, c3 = -dl * dl * dl * (1.f / 6.f);
             const float2 ERB = cis_cycles(cyc * (double)kFB);
             if (tid < kFB) {
                 float s, c;
@@ -170,8 +173,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
                 s_rot[tid] = make_float2(c, s);
             }
             float cr = 0.f, ci = 0.f;
-            for (int s0 = 0; s0 < a.L; s0 += kFT) {
-                const int tl = min(kFT, a.L - s0);
+            for (int s0 = 0; s0 < a.L; s0 += TB * kFB) {
+                const int tl = min(TB * kFB, a.L - s0);
                 const int nblk = (tl + kFB - 1) / kFB;
                 __syncthreads();
                 {
@@ -193,46 +196,55 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
                 }
                 __syncthreads();
                 float2 W = cis_cycles(cyc * ((double)s0 + 0.5 * (double)(kFB - 1) - centre));
-                for (int bb = 0; bb < nblk; bb += 4) {
-                    // phase 1: wave w forms the moments of block bb + w for every lag of the tile
-                    const int b = bb + wave;
-                    if (b < nblk) {
-                        for (int l0 = 0; l0 < H; l0 += 64) {
-                            const int l = l0 + lane;
-                            if (l < H) {
-                                float2 G[kFQ];
-                                const float2* v = s_v + b * kFB;
-                                const float2* y = s_y + b * kFB + l;
-                                switch (Q) {
-                                    case 1: block_moments<1>(v, y, G); break;
-                                    case 2: block_moments<2>(v, y, G); break;
-                                    case 3: block_moments<3>(v, y, G); break;
-                                    default: block_moments<4>(v, y, G); break;
-                                }
-#pragma unroll
-                                for (int q = 0; q < kFQ; ++q)
-                                    if (q < Q) s_G[wave][q][l] = G[q];
-                            }
+                for (int bb = 0; bb < nblk; bb += NB) {
+                    // phase 1: item (my_b, my_l) forms the moments of block bb + my_b at lag my_l
+                    const int b = bb + my_b;
+                    if (my_b < NB && b < nblk) {
+                        float2 G[kFQ];
+                        const float2* v = s_v + b * kFB;
+                        const float2* y = s_y + b * kFB + my_l;
+                        switch (Q) {
+                            case 1: block_moments<1>(v, y, G); break;
+                            case 2: block_moments<2>(v, y, G); break;
+                            case 3: block_moments<3>(v, y, G); break;
+                            default: block_moments<4>(v, y, G); break;
                         }
+#pragma unroll
+                        for (int q = 0; q < kFQ; ++q)
+                            if (q < Q) s_G[(my_b * Q + q) * H + my_l] = G[q];
                     }
                     __syncthreads();
                     // phase 2: every point combines 2Q moments per block
-                    const int nb = min(4, nblk - bb);
+                    const int nb = min(NB, nblk - bb);
                     for (int w = 0; w < nb; ++w) {
-                        float sr = 0.f, si = 0.f;
+                        const float2* g = s_G + w * Q * H + off;
+                        float m[kFQ][2];
 #pragma unroll
                         for (int q = 0; q < kFQ; ++q) {
                             if (q < Q) {
-                                const float2 g0 = s_G[w][q][off];
-                                float mr = g0.x, mi = g0.y;
+                                const float2 g0 = g[q * H];
+                                m[q][0] = g0.x;
+                                m[q][1] = g0.y;
                                 if constexpr (!kRound) {
-                                    const float2 g1 = s_G[w][q][off + 1];
-                                    mr = fmaf(alpha, g1.x - g0.x, g0.x);
-                                    mi = fmaf(alpha, g1.y - g0.y, g0.y);
+                                    const float2 g1 = g[q * H + 1];
+                                    m[q][0] = fmaf(alpha, g1.x - g0.x, g0.x);
+                                    m[q][1] = fmaf(alpha, g1.y - g0.y, g0.y);
                                 }
-                                sr = fmaf(aq[q].x, mr, fmaf(-aq[q].y, mi, sr));
-                                si = fmaf(aq[q].x, mi, fmaf(aq[q].y, mr, si));
                             }
+                        }
+                        // s = m0 + j c1 m1 + c2 m2 + j c3 m3
+                        float sr = m[0][0], si = m[0][1];
+                        if (Q > 1) {
+                            sr = fmaf(-c1, m[1][1], sr);
+                            si = fmaf(c1, m[1][0], si);
+                        }
+                        if (Q > 2) {
+                            sr = fmaf(c2, m[2][0], sr);
+                            si = fmaf(c2, m[2][1], si);
+                        }
+                        if (Q > 3) {
+                            sr = fmaf(-c3, m[3][1], sr);
+                            si = fmaf(c3, m[3][0], si);
                         }
                         cr = fmaf(W.x, sr, fmaf(-W.y, si, cr));
                         ci = fmaf(W.x, si, fmaf(W.y, sr, ci));

@@ -100,8 +100,9 @@ def load() -> ctypes.CDLL:
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
     lib.geoloc_strerror.restype = ctypes.c_char_p
     lib.geoloc_last_error.restype = ctypes.c_char_p
+    lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
-                 "geoloc_info", "geoloc_destroy"):
+                 "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -196,12 +197,34 @@ def geoloc_destroy(plan: int) -> None:
     _check(load().geoloc_destroy(plan), "geoloc_destroy")
 
 
+def geoloc_subbands(captures_dev: int, n_ch: int, n_samples: int, n_bands: int, half_taps: int, out_dev: int,
+                    stream: int) -> None:
+    _check(load().geoloc_subbands(captures_dev, n_ch, n_samples, n_bands, half_taps, out_dev, stream),
+           "geoloc_subbands")
+
+
 # --------------------------------------------------------------------------- torch-facing wrapper
 
 def _stream_handle(stream) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+def subbands(captures, n_bands: int, half_taps: int, out=None, stream=None):
+    """Sub-band split of complex64 CUDA captures [n_ch][N] -> [n_bands * n_ch][N / n_bands]
+    (band-major: band b of channel c is row b * n_ch + c)."""
+    import torch
+    if captures.dtype != torch.complex64 or not captures.is_cuda or not captures.is_contiguous():
+        raise ValueError("captures must be a contiguous complex64 CUDA tensor")
+    C, N = captures.shape
+    if out is None:
+        out = torch.empty((n_bands * C, N // n_bands), dtype=torch.complex64, device=captures.device)
+    elif (tuple(out.shape) != (n_bands * C, N // n_bands) or out.dtype != torch.complex64
+          or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous complex64 tensor [n_bands * n_ch][N / n_bands]")
+    geoloc_subbands(captures.data_ptr(), C, N, n_bands, half_taps, out.data_ptr(), _stream_handle(stream))
+    return out
 
 
 class Plan:

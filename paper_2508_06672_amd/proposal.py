@@ -2,10 +2,14 @@
 
 This is an addition to the method (the paper has no learned part). Pipeline for one
 scenario, every step through libgeoloc on the GPU:
-  1. coarse map: the plain direct map at the centres of the 64 x 64 tiles (16 x 16
-     fine cells each) of the fine grid;
-  2. features [log-compressed coarse map, TDOA and FDOA of the middle step] -> CNN ->
-     tile logits -> softmax -> the 16 most likely tiles;
+  1. coarse map: the captures are split into 16 frequency bands, each decimated by 16
+     (geoloc_subbands), and the plain direct map of every band (one receiver pair per
+     band, summed into one J) is evaluated at the centres of the 64 x 64 tiles (16 x 16
+     fine cells each) of the fine grid. At 1/16 of the sample rate the delay peak of a
+     wideband emitter is 16 samples wide, about one coarse cell, so the coarse grid does
+     not miss it between its points, and a narrowband emitter keeps its band;
+  2. features [log-compressed coarse map, TDOA (decimated samples) and FDOA of the
+     middle step] -> CNN -> tile logits -> softmax -> the 16 most likely tiles;
   3. refine: the plain direct map at the 16 x 256 fine cells of those tiles, argmax;
   4. fallback: when the softmax mass of the chosen tiles is below 0.5 (or, with
      rule="top1", the top tile's probability), the plain map over the full grid.
@@ -36,9 +40,10 @@ from . import configs, sim
 COARSE = configs.PROPOSAL_COARSE
 TILE = configs.PROPOSAL_TILE
 TOPK = configs.PROPOSAL_TOPK
+BANDS, BAND_HALF_TAPS = 16, 64          # coarse-map sub-bands: 16 bands, 129-tap low-pass
 LABEL_EPS = 1e-2
 IN_CH, HIDDEN, LAYERS = 3, 32, 4
-TRAIN_WL = configs.PROPOSAL.with_(name="proposal_train_1024x1024_10MHz_1e5", n_samples=100_000)
+TRAIN_WL = configs.PROPOSAL
 SEED_TRAIN, SEED_VAL, SEED_TEST = 1_000_000, 1_020_000, 1_030_000
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal_cnn.npz")
 
@@ -77,6 +82,18 @@ def tile_label(J: np.ndarray, n_rows: int, n_cols: int, tile: int = TILE, eps: f
     return (mask / mask.sum()).ravel().astype(np.float32)
 
 
+def band_states(states: np.ndarray, n_bands: int = BANDS) -> np.ndarray:
+    """Receiver states for the band-major sub-band captures: band b of receiver r is
+    receiver b * R + r, at the same position and velocity."""
+    st = np.asarray(states, dtype=np.float64)
+    return np.ascontiguousarray(np.tile(st, (1, n_bands, 1)))
+
+
+def band_pairs(pairs, n_rx: int, n_bands: int = BANDS):
+    """Each receiver pair within each band."""
+    return [(b * n_rx + i, b * n_rx + j) for b in range(n_bands) for (i, j) in pairs]
+
+
 def he_init(seed: int) -> np.ndarray:
     """He-normal convolution weights, zero biases, in the library's flat parameter order."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
@@ -110,7 +127,13 @@ class Proposer:
         clat, clon = coarse_axes(lat0, lon0)
         kw = dict(n_rx=wl.n_rx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
                   pairs=list(wl.pairs), earth_radius_m=wl.earth_radius_m)
-        self.coarse = geoloc.Plan(lat=clat, lon=clon, **kw)
+        if wl.n_samples % BANDS or wl.step_len % BANDS:
+            raise ValueError(f"capture and step lengths must be multiples of {BANDS}")
+        self.coarse = geoloc.Plan(n_rx=BANDS * wl.n_rx, n_samples=wl.n_samples // BANDS,
+                                  step_len=wl.step_len // BANDS, fs_hz=wl.fs_hz / BANDS, fc_hz=wl.fc_hz,
+                                  pairs=band_pairs(wl.pairs, wl.n_rx), earth_radius_m=wl.earth_radius_m,
+                                  lat=clat, lon=clon)
+        self._bands = None
         plat, plon, _ = tile_points(lat0, lon0, range(topk))
         self.refine = geoloc.Plan(lat=plat, lon=plon, grid_kind=geoloc.GRID_POINTS, **kw)
         self.full = geoloc.Plan(lat=lat0, lon=lon0, **kw)
@@ -124,8 +147,14 @@ class Proposer:
 
     def coarse_features(self, caps, states):
         """(coarse map [64*64], CNN input [1, 3, 64, 64])."""
-        Jc = self.coarse.map(caps, states)
-        D, nu = self.coarse.geometry(states, 0, self.wl.n_steps // 2, 1)
+        import torch
+        if self._bands is None:
+            self._bands = torch.empty((BANDS * self.wl.n_rx, self.wl.n_samples // BANDS), dtype=torch.complex64,
+                                      device=caps.device)
+        z = self.G.subbands(caps, BANDS, BAND_HALF_TAPS, out=self._bands)
+        st = band_states(states)
+        Jc = self.coarse.map(z, st)
+        D, nu = self.coarse.geometry(st, 0, self.wl.n_steps // 2, 1)
         x = self.net.prepare(Jc.view(1, -1), D, nu)
         return Jc, x
 
@@ -330,7 +359,7 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--n-train", type=int, default=8000)
+    t.add_argument("--n-train", type=int, default=6000)
     t.add_argument("--n-val", type=int, default=200)
     t.add_argument("--epochs", type=int, default=20)
     t.add_argument("--lr", type=float, default=2e-3)

@@ -126,3 +126,25 @@ def test_no_device_returns_edevice():
     assert out.returncode == 0, out.stderr
     rc, hv = out.stdout.split()[:2]
     assert int(rc) == geoloc.EDEVICE and hv == "None", out.stdout
+
+
+def test_subbands_validation_returns_einval():
+    """Argument checks of the sub-band split happen before any device call."""
+    lib = geoloc.load()
+    buf = ctypes.c_void_p(4096)          # never dereferenced: each call fails validation first
+    cases = [
+        (None, 2, 1600, 16, 64, buf),          # null input
+        (buf, 2, 1600, 16, 64, None),          # null output
+        (ctypes.c_void_p(4100), 2, 1600, 16, 64, buf),   # misaligned
+        (buf, 0, 1600, 16, 64, buf),           # no channels
+        (buf, 2, 0, 16, 64, buf),              # no samples
+        (buf, 2, 1600, 0, 64, buf),            # no bands
+        (buf, 2, 1600, 64, 16, buf),           # too many bands
+        (buf, 2, 1601, 16, 64, buf),           # samples not divisible by bands
+        (buf, 2, 1600, 16, 0, buf),            # no taps
+        (buf, 2, 1600, 16, 129, buf),          # too many taps
+        (buf, 2, 1600, 32, 100, buf),          # band table too large
+    ]
+    for c in cases:
+        rc = lib.geoloc_subbands(c[0], c[1], c[2], c[3], c[4], c[5], None)
+        assert rc == geoloc.EINVAL, (c, rc, geoloc.geoloc_last_error())

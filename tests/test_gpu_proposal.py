@@ -6,7 +6,7 @@ import os
 import numpy as np
 import pytest
 
-from helpers import log, require_gpu
+from helpers import err_J, log, require_gpu
 from paper_2508_06672_amd import configs, sim
 
 pytestmark = pytest.mark.gpu
@@ -45,8 +45,11 @@ def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
 
 
 def test_refined_tiles_reproduce_the_full_map(torch, P):
-    """The refine map at the chosen tiles' cells equals the full map at those cells, and
-    when the chosen tiles contain the full map's peak the refined peak is that peak."""
+    """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals, bit
+    for bit, the full-grid map at those cells: the same tile-factored kernel sees the same
+    256 points per workgroup and the same step split. The per-point kernel agrees to FP32
+    rounding. When the chosen tiles contain the full map's peak the refined peak is that
+    peak."""
     from paper_2508_06672_amd import geoloc
     wl = SMALL_WL
     net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
@@ -56,6 +59,9 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     prop.set_grid(scn.lat, scn.lon)
     a_full, v_full, Jf = prop.full_map(caps, scn.states)
     Jf = Jf.cpu().numpy()
+    with geoloc.Plan.for_scenario(scn, method=geoloc.DIRECT_FP32_POINTWISE) as pw:
+        Jp = pw.map(caps, scn.states).cpu().numpy()
+    assert err_J(Jf.astype(np.float64), Jp.astype(np.float64)) <= 2e-5
     tile_of = (a_full // wl.n_cols // P.TILE) * (wl.n_cols // P.TILE) + (a_full % wl.n_cols) // P.TILE
     tiles = [tile_of] + [t for t in range(P.TOPK) if t != tile_of][: P.TOPK - 1]
     plat, plon, idx = P.tile_points(scn.lat, scn.lon, tiles)
