@@ -45,6 +45,10 @@ class Workload:
     snr_db_range: Tuple[float, float] | None = None
     n_emitters: int = 1
     pairs: Tuple[Tuple[int, int], ...] = ((0, 1),)
+    # separate captures (snapshots) of n_samples each, their centres spaced in time; the
+    # map of a scenario accumulates over them (Sec. IV-B: 58 captures 1 s apart)
+    n_snapshots: int = 1
+    snapshot_spacing_s: float = 0.0
 
     @property
     def n_steps(self) -> int:
@@ -60,8 +64,8 @@ class Workload:
 
     @property
     def units(self) -> int:
-        """grid-point x sample correlations in one full map."""
-        return self.n_points * self.n_samples * len(self.pairs)
+        """grid-point x sample correlations in one full map (all snapshots)."""
+        return self.n_points * self.n_samples * len(self.pairs) * self.n_snapshots
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
@@ -87,11 +91,14 @@ CAF_LAGS = 512
 CAF_BINS = 256
 CAF_LITERAL_WINDOW_HZ = (-40e3, 40e3)
 
-# Learned proposal: 1024 x 1024 fine grid at 0.5 km, 64 x 64 coarse cells of 8 km.
+# Learned proposal: 1024 x 1024 fine grid at 0.5 km, 64 x 64 coarse cells of 8 km; 10 separate
+# 10 ms captures (one coherent step each) 4 s apart, so that the changing geometry turns the
+# single-capture delay / Doppler ridges into a peak (Sec. IV-B accumulates 58 captures 1 s apart).
 PROPOSAL = MAP_1E6.with_(
-    name="proposal_1024x1024_10MHz_1e6",
+    name="proposal_1024x1024_10MHz_10x10ms",
     n_rows=1024, n_cols=1024, waveform="tone|chirp|gauss",
     snr_db=-10.0, snr_db_range=(-20.0, 0.0),
+    n_samples=100_000, step_len=100_000, n_snapshots=10, snapshot_spacing_s=4.0,
 )
 PROPOSAL_COARSE = 64
 PROPOSAL_TILE = 16

@@ -63,7 +63,7 @@ struct geoloc_plan_s {
     int2* d_pairs = nullptr;
     double* d_D = nullptr;
     double* d_nu = nullptr;
-    double* d_partial = nullptr;     // [step groups][P] when a plan's grid is too small to fill the GPU
+    double* d_partial = nullptr;     // [item groups][P] when a plan's grid is too small to fill the GPU
     int32_t n_groups = 1;
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
     bool use_fact = false;           // factored direct kernel (method GEOLOC_DIRECT_FP32)
@@ -606,7 +606,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
         if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
-        p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, p->kc);
+        p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, (int64_t)p->kc * p->n_pairs);
         if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
         p->use_fact = p->method == GEOLOC_DIRECT_FP32;
         if (p->use_fact &&
@@ -717,7 +717,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.inv_fs = 1.0 / p->fs;
         a.accum_mode = p->accum_mode;
         a.load_J = (k0 > 0) || (flags & GEOLOC_ACCUMULATE);
-        a.n_groups = std::min<int32_t>(p->n_groups, kc);
+        a.n_groups = (int32_t)std::min<int64_t>(p->n_groups, (int64_t)kc * p->n_pairs);
         a.partial = p->d_partial;
         a.mask = nullptr;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;

@@ -45,7 +45,7 @@ struct DirectArgs {
     double inv_fs;
     int32_t accum_mode;
     int32_t load_J;          // add onto the existing J values
-    int32_t n_groups;        // step groups per chunk (1: each workgroup owns its points' J)
+    int32_t n_groups;        // groups of (pair, step) items per chunk (1: each workgroup owns its points' J)
     double* partial;         // [n_groups][P] partial sums when n_groups > 1
     const uint8_t* mask;     // [n_pairs][kc][n_tiles]: nonzero = this kernel handles it; NULL = all
 };
@@ -60,8 +60,8 @@ __device__ inline float2 cis_cycles(double cyc) {
 
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s);
 
-constexpr int32_t kMaxStepGroups = 64;
-int32_t direct_groups(int64_t n_tiles, int32_t kc);
+constexpr int32_t kMaxItemGroups = 64;
+int32_t direct_groups(int64_t n_tiles, int64_t n_items);   // n_items = pairs x steps per chunk
 
 struct GeomArgs {
     const double* xyz;       // [P][3]
@@ -141,7 +141,7 @@ hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_k
                             double radius, double* xyz, hipStream_t s);
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s);
 hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s);
-// with step groups, adds the [n_groups][P] partial sums into J (onto J when load_J)
+// with item groups, adds the [n_groups][P] partial sums into J (onto J when load_J)
 hipError_t launch_direct_reduce(const DirectArgs& a, hipStream_t s);
 
 struct ArgmaxScratch {

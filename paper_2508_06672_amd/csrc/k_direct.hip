@@ -130,25 +130,29 @@ void k_direct(DirectArgs a) {
     __shared__ int s_mm[2][4];
 
     const int tid = threadIdx.x;
-    // workgroup -> (point tile, step group): with n_groups > 1 each group sums its share of
-    // the chunk's steps into its own partial row, reduced afterwards in a fixed order
+    // workgroup -> (point tile, group): with n_groups > 1 each group sums its share of the
+    // chunk's (pair, step) items, pair-major, into its own partial row, reduced afterwards
+    // in a fixed order
     const int64_t tile = blockIdx.x % a.n_tiles;
     const int group = (int)(blockIdx.x / a.n_tiles);
-    const int kk_lo = (int)((int64_t)a.kc * group / a.n_groups);
-    const int kk_hi = (int)((int64_t)a.kc * (group + 1) / a.n_groups);
+    const int64_t n_items = (int64_t)a.n_pairs * a.kc;
+    const int64_t it_lo = n_items * group / a.n_groups;
+    const int64_t it_hi = n_items * (group + 1) / a.n_groups;
     bool valid;
     const int64_t p = tile_point(a.tiling, tile, tid, &valid);
-    // step groups: a masked pass adds onto the partial sums the factored kernel wrote
+    // item groups: a masked pass adds onto the partial sums the factored kernel wrote
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
     if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
     const double centre = 0.5 * (double)(a.L - 1);
 
-    for (int e = 0; e < a.n_pairs; ++e) {
+    for (int64_t it = it_lo; it < it_hi; ++it) {
+        const int e = (int)(it / a.kc);
+        const int kk = (int)(it - (int64_t)e * a.kc);
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
-        for (int kk = kk_lo; kk < kk_hi; ++kk) {
+        {
             // with a mask, only the (tile, step) pairs the factored kernel left over
             if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
@@ -222,7 +226,7 @@ void k_direct(DirectArgs a) {
         a.partial[(int64_t)group * a.P + p] = jacc;
 }
 
-// J[p] = (J[p] if loading) + sum over step groups of the partial sums, in group order.
+// J[p] = (J[p] if loading) + sum over item groups of the partial sums, in group order.
 __global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict__ partial, int32_t n_groups, int64_t P,
                                                        int32_t load_J, float* __restrict__ J) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -232,11 +236,11 @@ __global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict_
     J[p] = (float)acc;
 }
 
-int32_t direct_groups(int64_t n_tiles, int32_t kc) {
+int32_t direct_groups(int64_t n_tiles, int64_t n_items) {
     // enough workgroups to cover 256 CUs several times over
     int64_t g = (1024 + n_tiles - 1) / n_tiles;
-    if (g > kc) g = kc;
-    if (g > kMaxStepGroups) g = kMaxStepGroups;
+    if (g > n_items) g = n_items;
+    if (g > kMaxItemGroups) g = kMaxItemGroups;
     return (int32_t)(g < 1 ? 1 : g);
 }
 

@@ -102,22 +102,25 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
     __shared__ float s_f[2][4];
 
     const int tid = threadIdx.x;
-    // workgroup -> (point tile, step group), as in the per-point kernel
+    // workgroup -> (point tile, group of (pair, step) items), as in the per-point kernel
     const int64_t tile = blockIdx.x % a.n_tiles;
     const int group = (int)(blockIdx.x / a.n_tiles);
-    const int kk_lo = (int)((int64_t)a.kc * group / a.n_groups);
-    const int kk_hi = (int)((int64_t)a.kc * (group + 1) / a.n_groups);
+    const int64_t n_items = (int64_t)a.n_pairs * a.kc;
+    const int64_t it_lo = n_items * group / a.n_groups;
+    const int64_t it_hi = n_items * (group + 1) / a.n_groups;
     bool valid;
     const int64_t p = tile_point(a.tiling, tile, tid, &valid);
     double jacc = (valid && a.load_J && a.n_groups == 1) ? (double)a.J[p] : 0.0;
     const double centre = 0.5 * (double)(a.L - 1);
     const double two_pi = 6.283185307179586476925;
 
-    for (int e = 0; e < a.n_pairs; ++e) {
+    for (int64_t it = it_lo; it < it_hi; ++it) {
+        const int e = (int)(it / a.kc);
+        const int kk = (int)(it - (int64_t)e * a.kc);
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
-        for (int kk = kk_lo; kk < kk_hi; ++kk) {
+        {
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
             const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
             double D = valid ? a.D[gi] : 0.0;

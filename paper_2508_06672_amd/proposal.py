@@ -82,6 +82,17 @@ def tile_label(J: np.ndarray, n_rows: int, n_cols: int, tile: int = TILE, eps: f
     return (mask / mask.sum()).ravel().astype(np.float32)
 
 
+def stack_snapshots(snaps, pairs):
+    """Separate captures as virtual receivers of one map call: receiver r of snapshot s is
+    receiver s * R + r, with that snapshot's states, and each pair is repeated within each
+    snapshot. Returns (captures [S*R][N], states [K][S*R][6], pairs)."""
+    R = snaps[0].captures.shape[0]
+    caps = np.ascontiguousarray(np.concatenate([sc.captures for sc in snaps], axis=0))
+    states = np.ascontiguousarray(np.concatenate([sc.states for sc in snaps], axis=1))
+    vpairs = [(s * R + i, s * R + j) for s in range(len(snaps)) for (i, j) in pairs]
+    return caps, states, vpairs
+
+
 def band_states(states: np.ndarray, n_bands: int = BANDS) -> np.ndarray:
     """Receiver states for the band-major sub-band captures: band b of receiver r is
     receiver b * R + r, at the same position and velocity."""
@@ -117,7 +128,8 @@ def load_weights(path: str = WEIGHTS):
 # --------------------------------------------------------------------------- the proposer
 
 class Proposer:
-    """Plans and network for one fine-grid shape; set_grid() retargets a scenario."""
+    """Plans and network for one fine-grid shape; set_grid() retargets a scenario. Maps take
+    the scenario's snapshots stacked as virtual receivers (stack_snapshots)."""
 
     def __init__(self, wl, net, topk: int = TOPK, threshold: float = 0.5, rule: str = "mass"):
         from . import geoloc
@@ -125,13 +137,16 @@ class Proposer:
         self.wl, self.net, self.topk, self.threshold, self.rule = wl, net, topk, threshold, rule
         lat0, lon0 = sim.make_grid(wl, 0.0)
         clat, clon = coarse_axes(lat0, lon0)
-        kw = dict(n_rx=wl.n_rx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
-                  pairs=list(wl.pairs), earth_radius_m=wl.earth_radius_m)
+        # every snapshot's receivers as virtual receivers of one map call
+        self.n_vrx = wl.n_snapshots * wl.n_rx
+        self.vpairs = [(s * wl.n_rx + i, s * wl.n_rx + j) for s in range(wl.n_snapshots) for (i, j) in wl.pairs]
+        kw = dict(n_rx=self.n_vrx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                  pairs=self.vpairs, earth_radius_m=wl.earth_radius_m)
         if wl.n_samples % BANDS or wl.step_len % BANDS:
             raise ValueError(f"capture and step lengths must be multiples of {BANDS}")
-        self.coarse = geoloc.Plan(n_rx=BANDS * wl.n_rx, n_samples=wl.n_samples // BANDS,
+        self.coarse = geoloc.Plan(n_rx=BANDS * self.n_vrx, n_samples=wl.n_samples // BANDS,
                                   step_len=wl.step_len // BANDS, fs_hz=wl.fs_hz / BANDS, fc_hz=wl.fc_hz,
-                                  pairs=band_pairs(wl.pairs, wl.n_rx), earth_radius_m=wl.earth_radius_m,
+                                  pairs=band_pairs(self.vpairs, self.n_vrx), earth_radius_m=wl.earth_radius_m,
                                   lat=clat, lon=clon)
         self._bands = None
         plat, plon, _ = tile_points(lat0, lon0, range(topk))
@@ -149,12 +164,14 @@ class Proposer:
         """(coarse map [64*64], CNN input [1, 3, 64, 64])."""
         import torch
         if self._bands is None:
-            self._bands = torch.empty((BANDS * self.wl.n_rx, self.wl.n_samples // BANDS), dtype=torch.complex64,
+            self._bands = torch.empty((BANDS * self.n_vrx, self.wl.n_samples // BANDS), dtype=torch.complex64,
                                       device=caps.device)
         z = self.G.subbands(caps, BANDS, BAND_HALF_TAPS, out=self._bands)
         st = band_states(states)
         Jc = self.coarse.map(z, st)
-        D, nu = self.coarse.geometry(st, 0, self.wl.n_steps // 2, 1)
+        # TDOA / FDOA features: the first pair of the middle snapshot, band 0, middle step
+        mid = (self.wl.n_snapshots // 2) * len(self.wl.pairs)
+        D, nu = self.coarse.geometry(st, mid, self.wl.n_steps // 2, 1)
         x = self.net.prepare(Jc.view(1, -1), D, nu)
         return Jc, x
 
@@ -198,8 +215,10 @@ class Proposer:
 
 def _simulate(args):
     wl, seed = args
-    s = sim.make_scenario(wl, seed)
-    return seed, s.lat, s.lon, s.states, s.captures, s.emitters[0].waveform, s.snr_db
+    snaps = sim.make_snapshots(wl, seed)
+    caps, states, _ = stack_snapshots(snaps, wl.pairs)
+    s = snaps[0]
+    return seed, s.lat, s.lon, states, caps, s.emitters[0].waveform, s.snr_db
 
 
 def scenario_stream(wl, seeds: Sequence[int], pool=None):

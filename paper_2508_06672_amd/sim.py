@@ -215,11 +215,19 @@ def _pick_waveform(wl: Workload, rng: np.random.Generator) -> str:
 
 def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noiseless: bool = False,
                   emitter_latlon: Optional[List[Tuple[float, float]]] = None,
-                  waveform: Optional[str] = None) -> Scenario:
+                  waveform: Optional[str] = None, t_offset_s: float = 0.0, stream: int = 0) -> Scenario:
+    """One capture of n_samples centred t_offset_s after the reference instant of the
+    seed's geometry. Geometry, emitter and SNR come from the seed alone; `stream` > 0
+    draws the waveform and the receiver noise from a stream of their own (the separate
+    snapshots of one scenario)."""
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(3 + max(3, wl.n_rx))
     rng_geo, rng_em, rng_wave = (np.random.Generator(np.random.PCG64(k)) for k in kids[:3])
     rng_noise = [np.random.Generator(np.random.PCG64(k)) for k in kids[3:3 + wl.n_rx]]
+    if stream:
+        sk = np.random.SeedSequence(seed, spawn_key=(1_000_000 + int(stream),)).spawn(1 + wl.n_rx)
+        rng_wave = np.random.Generator(np.random.PCG64(sk[0]))
+        rng_noise = [np.random.Generator(np.random.PCG64(k)) for k in sk[1:]]
 
     u_mid = float(rng_geo.uniform(0.0, 2.0 * math.pi))
     lat, lon = make_grid(wl, u_mid)
@@ -242,7 +250,7 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
         emitters.append(Emitter(la, lo, wf, f0, power))
 
     N, fs = wl.n_samples, wl.fs_hz
-    t_abs = np.arange(N, dtype=np.float64) / fs
+    t_abs = t_offset_s + np.arange(N, dtype=np.float64) / fs
     t_rel = t_abs - (N - 1) / (2.0 * fs)
     st = receiver_states(wl, u_mid, t_rel)                        # [N][R][6]
 
@@ -281,11 +289,27 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
             g = rng_noise[i]
             y[i] += sd * (g.standard_normal(N) + 1j * g.standard_normal(N))
 
-    states = receiver_states(wl, u_mid, step_centre_times(wl))
+    states = receiver_states(wl, u_mid, t_offset_s + step_centre_times(wl))
     true_cells = [nearest_cell(lat, lon, em.lat, em.lon) for em in emitters]
     mirror_cells = [nearest_cell(lat, lon, *mirror_latlon(wl, em.lat, em.lon)) for em in emitters]
     return Scenario(wl, seed, lat, lon, states, np.ascontiguousarray(y.astype(np.complex64)),
                     emitters, true_cells, mirror_cells, noise_var, snr_db, u_mid)
+
+
+def snapshot_offsets(wl: Workload) -> np.ndarray:
+    """Centre times of the snapshots relative to the reference instant, symmetric."""
+    s = np.arange(wl.n_snapshots, dtype=np.float64)
+    return (s - (wl.n_snapshots - 1) / 2.0) * wl.snapshot_spacing_s
+
+
+def make_snapshots(wl: Workload, seed: int, **kw) -> List[Scenario]:
+    """The wl.n_snapshots separate captures of one scenario (same grid, emitter and SNR;
+    own waveform and noise draws, receivers further along their orbits). One snapshot
+    is exactly make_scenario(wl, seed)."""
+    if wl.n_snapshots == 1:
+        return [make_scenario(wl, seed, **kw)]
+    return [make_scenario(wl, seed, t_offset_s=float(t), stream=i + 1, **kw)
+            for i, t in enumerate(snapshot_offsets(wl))]
 
 
 def points_of(scn: Scenario) -> Tuple[np.ndarray, np.ndarray]:

@@ -25,7 +25,13 @@ def P():
 
 
 SMALL_WL = configs.PROPOSAL.with_(name="proposal_small", n_rows=128, n_cols=160, n_samples=40_000,
-                                  waveform="chirp")
+                                  step_len=10_000, n_snapshots=3, waveform="chirp")
+
+
+def _scenario(P, wl, seed):
+    snaps = sim.make_snapshots(wl, seed)
+    caps, states, _ = P.stack_snapshots(snaps, wl.pairs)
+    return snaps[0], caps, states
 
 
 def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
@@ -33,11 +39,11 @@ def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
     wl = SMALL_WL
     net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
     prop = P.Proposer(wl, net)
-    scn = sim.make_scenario(wl, 1)
-    caps = torch.from_numpy(scn.captures).cuda()
+    scn, capn, states = _scenario(P, wl, 1)
+    caps = torch.from_numpy(capn).cuda()
     prop.set_grid(scn.lat, scn.lon)
-    r = prop.run(caps, scn.states)
-    a_full, v_full, _ = prop.full_map(caps, scn.states)
+    r = prop.run(caps, states)
+    a_full, v_full, _ = prop.full_map(caps, states)
     assert r["fallback"] and abs(r["score"] - P.TOPK / (8 * 10)) < 1e-5
     assert r["idx"] == a_full and r["val"] == v_full
     prop.close()
@@ -54,21 +60,23 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     wl = SMALL_WL
     net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
     prop = P.Proposer(wl, net)
-    scn = sim.make_scenario(wl, 2)
-    caps = torch.from_numpy(scn.captures).cuda()
+    scn, capn, states = _scenario(P, wl, 2)
+    caps = torch.from_numpy(capn).cuda()
     prop.set_grid(scn.lat, scn.lon)
-    a_full, v_full, Jf = prop.full_map(caps, scn.states)
+    a_full, v_full, Jf = prop.full_map(caps, states)
     Jf = Jf.cpu().numpy()
-    with geoloc.Plan.for_scenario(scn, method=geoloc.DIRECT_FP32_POINTWISE) as pw:
-        Jp = pw.map(caps, scn.states).cpu().numpy()
+    with geoloc.Plan(n_rx=prop.n_vrx, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz,
+                     fc_hz=wl.fc_hz, lat=scn.lat, lon=scn.lon, pairs=prop.vpairs, earth_radius_m=wl.earth_radius_m,
+                     method=geoloc.DIRECT_FP32_POINTWISE) as pw:
+        Jp = pw.map(caps, states).cpu().numpy()
     assert err_J(Jf.astype(np.float64), Jp.astype(np.float64)) <= 2e-5
     tile_of = (a_full // wl.n_cols // P.TILE) * (wl.n_cols // P.TILE) + (a_full % wl.n_cols) // P.TILE
     tiles = [tile_of] + [t for t in range(P.TOPK) if t != tile_of][: P.TOPK - 1]
     plat, plon, idx = P.tile_points(scn.lat, scn.lon, tiles)
     prop.refine.set_grid(plat, plon)
-    Jr = prop.refine.map(caps, scn.states).cpu().numpy()
+    Jr = prop.refine.map(caps, states).cpu().numpy()
     assert np.array_equal(Jr, Jf[idx])
-    i, v = prop.refine_tiles(caps, scn.states, tiles)
+    i, v = prop.refine_tiles(caps, states, tiles)
     assert i == a_full and v == v_full
     prop.close()
     net.close()

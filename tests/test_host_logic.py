@@ -1,0 +1,56 @@
+"""Host-side logic that needs no GPU: separate captures (snapshots) of one scenario, and
+their layout as virtual receivers of one map call, for the proposal workload."""
+import numpy as np
+
+from oracle import subband as osub
+from paper_2508_06672_amd import configs, sim
+from paper_2508_06672_amd import proposal as P
+
+
+def test_one_snapshot_is_the_plain_scenario():
+    wl = configs.SMALL.with_(n_samples=8000)
+    a = sim.make_snapshots(wl, 4)
+    b = sim.make_scenario(wl, 4)
+    assert len(a) == 1
+    assert np.array_equal(a[0].captures, b.captures) and np.array_equal(a[0].states, b.states)
+
+
+def test_snapshots_share_the_scenario_and_advance_the_orbit():
+    wl = configs.PROPOSAL.with_(n_rows=32, n_cols=32, n_samples=20_000, step_len=10_000, n_snapshots=4,
+                                snapshot_spacing_s=3.0)
+    snaps = sim.make_snapshots(wl, 9)
+    assert len(snaps) == 4
+    offs = sim.snapshot_offsets(wl)
+    assert np.allclose(offs, [-4.5, -1.5, 1.5, 4.5])
+    for s, sc in enumerate(snaps):
+        assert np.array_equal(sc.lat, snaps[0].lat) and np.array_equal(sc.lon, snaps[0].lon)
+        assert (sc.emitters[0].lat, sc.emitters[0].lon) == (snaps[0].emitters[0].lat, snaps[0].emitters[0].lon)
+        assert sc.snr_db == snaps[0].snr_db
+        # states are the orbit at this snapshot's step centres
+        ref = sim.receiver_states(wl, sc.u_mid, offs[s] + sim.step_centre_times(wl))
+        assert np.array_equal(sc.states, ref)
+    # independent noise and waveform draws per snapshot
+    assert not np.array_equal(snaps[0].captures, snaps[1].captures)
+    # the receivers move about 7.6 km/s x 3 s between snapshots
+    d = np.linalg.norm(snaps[1].states[0, 0, :3] - snaps[0].states[0, 0, :3])
+    assert 20e3 < d < 25e3
+
+
+def test_stacked_snapshots_are_virtual_receivers():
+    wl = configs.PROPOSAL.with_(n_rows=16, n_cols=16, n_samples=3200, step_len=1600, n_snapshots=3,
+                                snapshot_spacing_s=2.0)
+    snaps = sim.make_snapshots(wl, 2)
+    caps, states, pairs = P.stack_snapshots(snaps, wl.pairs)
+    R = wl.n_rx
+    assert caps.shape == (3 * R, wl.n_samples) and states.shape == (wl.n_steps, 3 * R, 6)
+    assert pairs == [(0, 1), (2, 3), (4, 5)]
+    for s in range(3):
+        assert np.array_equal(caps[s * R:(s + 1) * R], snaps[s].captures)
+        assert np.array_equal(states[:, s * R:(s + 1) * R], snaps[s].states)
+
+
+def test_band_layout_matches_the_oracle_helpers():
+    st = np.random.default_rng(0).standard_normal((3, 6, 6))
+    assert np.array_equal(P.band_states(st, 4), osub.states_for_bands(st, 4))
+    pr = [(0, 1), (2, 3), (4, 5)]
+    assert P.band_pairs(pr, 6, 4) == osub.pairs_for_bands(pr, 6, 4)
