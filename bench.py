@@ -232,6 +232,30 @@ def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
             "within_one_cell_or_tol_optimal": optimal / n}
 
 
+def learned_leg(geoloc, seeds):
+    """The learned tile proposal with its stored weights and calibrated fallback on held-out
+    proposal scenarios: median time against the full plain map of the same scenario, and
+    how often its argmax agrees with the full map's (within one cell, on the orbital-plane
+    mirror, or tol-optimal), beside the coarse-map top-16 ablation."""
+    from paper_2508_06672_amd import proposal as P
+    theta, meta = P.load_weights()
+    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=1)
+    net.set_params(theta)
+    wl = P.TRAIN_WL
+    prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"))
+    try:
+        res = P.evaluate(prop, wl, seeds, None)
+    finally:
+        prop.close()
+        net.close()
+    L, A = res["learned"], res["coarse_top16_ablation"]
+    return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"],
+            "threshold": meta["threshold"], "full_map_median_ms": res["full_map_median_ms"],
+            "median_ms": L["median_ms"], "speedup_vs_full_median": L["speedup_vs_full_median"],
+            "agree_rate": L["agree_rate"], "fallback_rate": L["fallback_rate"],
+            "ablation_agree_rate": A["agree_rate"], "ablation_speedup_vs_full_median": A["speedup_vs_full_median"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +267,8 @@ def main() -> int:
     ap.add_argument("--no-caf", action="store_true", help="skip the CAF-table legs")
     ap.add_argument("--agreement-seeds", type=int, default=8,
                     help="scenarios (seeds 10000..) for the CAF-vs-direct argmax agreement")
+    ap.add_argument("--proposal-seeds", type=int, default=8,
+                    help="held-out scenarios for the learned-proposal leg (0 skips it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -331,6 +357,12 @@ def main() -> int:
             log(f"caf agreement over {args.agreement_seeds} seeds")
             caf["agreement_bf16"] = agreement(geoloc, torch, wl, list(range(10000, 10000 + args.agreement_seeds)))
 
+    learned = None
+    if args.proposal_seeds > 0:
+        from paper_2508_06672_amd import proposal as P
+        log(f"learned proposal over {args.proposal_seeds} held-out scenarios")
+        learned = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.proposal_seeds)))
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scn, args.cpu_seconds)
@@ -351,6 +383,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "caf": caf,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
     plan.close()

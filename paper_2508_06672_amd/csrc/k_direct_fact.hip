@@ -17,8 +17,11 @@
 // The moments G_q(b, d) depend on the lag only, not on the point, so a tile computes them
 // once for its few dozen lags and every point combines 2Q of them per block: about 2 VALU
 // instructions per grid-point x sample correlation instead of 13 for the per-point form.
-// The moment work is spread over the workgroup as (block, lag) items, floor(256 / H) blocks
-// of H lags per round, so that few lanes idle whatever the tile's lag spread H. Q is chosen
+// The moment work is spread over the workgroup as (block, lag pair) items, floor(256 /
+// ceil(H / 2)) blocks per round, so that few lanes idle whatever the tile's lag spread H;
+// the two lags of a lane share every sample read but one, which halves the LDS reads.
+// Each block's reference samples sit 66 words apart in LDS, so that the blocks that share
+// a wave read different banks. The step body is compiled per Taylor order. Q is chosen
 // per tile and step so that the Taylor remainder bound is at most one FP32 unit roundoff
 // (2^-24) of the block's magnitude sum, below the rounding of the block sum itself; a tile
 // whose lag spread exceeds kFH or whose Doppler spread needs more than kFQ terms is flagged
@@ -35,6 +38,7 @@ constexpr int kFTB = 16;         // most blocks per LDS tile
 constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
 constexpr int kFQ = 4;           // most Taylor terms
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
+constexpr int kFVS = kFB + 2;    // LDS stride of the reference samples of one block
 constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
 
 // Workgroup min / max of two ints and two floats (wave shuffles, then LDS).
@@ -61,42 +65,144 @@ __device__ inline void wg_extent(int& dlo, int& dhi, float& tlo, float& thi, int
     thi = fmaxf(fmaxf(sf[1][0], sf[1][1]), fmaxf(sf[1][2], sf[1][3]));
 }
 
-// Moments of one block for lag lane l: G[q] = sum_r r^q v[r] conj(y[r + l]).
+// Moments of one block for the lag pair (l, l + 1) of this lane, y = s_y + block start + l:
+// G0[q] = sum_r r'^q v[r] conj(y[r]), G1[q] = sum_r r'^q v[r] conj(y[r + 1]), r' = r - 31.5.
 template <int Q>
-__device__ inline void block_moments(const float2* __restrict__ v, const float2* __restrict__ y, float2 (&G)[kFQ]) {
+__device__ inline void block_moments2(const float2* __restrict__ v, const float2* __restrict__ y, float2 (&G0)[Q],
+                                      float2 (&G1)[Q]) {
 #pragma unroll
-    for (int q = 0; q < kFQ; ++q) G[q] = make_float2(0.f, 0.f);
+    for (int q = 0; q < Q; ++q) {
+        G0[q] = make_float2(0.f, 0.f);
+        G1[q] = make_float2(0.f, 0.f);
+    }
+    float2 t0 = y[0];
 #pragma unroll
     for (int r = 0; r < kFB; ++r) {
         const float2 x = v[r];
-        const float2 t = y[r];
-        const float zr = fmaf(x.x, t.x, x.y * t.y);     // x * conj(t)
-        const float zi = fmaf(x.y, t.x, -(x.x * t.y));
-        G[0].x += zr;
-        G[0].y += zi;
-        if constexpr (Q > 1) {
-            const float rr = (float)r - 0.5f * (float)(kFB - 1);
-            G[1].x = fmaf(rr, zr, G[1].x);
-            G[1].y = fmaf(rr, zi, G[1].y);
-            if constexpr (Q > 2) {
-                const float r2 = rr * rr;
-                G[2].x = fmaf(r2, zr, G[2].x);
-                G[2].y = fmaf(r2, zi, G[2].y);
-                if constexpr (Q > 3) {
-                    const float r3 = r2 * rr;
-                    G[3].x = fmaf(r3, zr, G[3].x);
-                    G[3].y = fmaf(r3, zi, G[3].y);
-                }
+        const float2 t1 = y[r + 1];
+        const float z0r = fmaf(x.x, t0.x, x.y * t0.y);     // x * conj(t0)
+        const float z0i = fmaf(x.y, t0.x, -(x.x * t0.y));
+        const float z1r = fmaf(x.x, t1.x, x.y * t1.y);     // x * conj(t1)
+        const float z1i = fmaf(x.y, t1.x, -(x.x * t1.y));
+        G0[0].x += z0r;
+        G0[0].y += z0i;
+        G1[0].x += z1r;
+        G1[0].y += z1i;
+        const float rr = (float)r - 0.5f * (float)(kFB - 1);
+        float w = 1.f;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            w *= rr;                                    // a compile-time constant per (r, q)
+            G0[q].x = fmaf(w, z0r, G0[q].x);
+            G0[q].y = fmaf(w, z0i, G0[q].y);
+            G1[q].x = fmaf(w, z1r, G1[q].x);
+            G1[q].y = fmaf(w, z1i, G1[q].y);
+        }
+        t0 = t1;
+    }
+}
+
+// Values of one (tile, step) that both phases use.
+struct FactStep {
+    int64_t n_step;        // first sample of the step
+    double cyc;            // this lane's FDOA in cycles per sample
+    float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
+    float alpha;           // this lane's fractional lag
+    float c1, c2, c3;      // Taylor coefficients of the lane's Doppler deviation
+    int dlo, Hs, NB, TB;   // lowest lag, lag stride of s_G (even), blocks per round / per LDS tile
+    int my_b, my_l, off;   // this thread's (block, lag pair) item; this lane's lag offset
+};
+
+// One (tile, step): stage samples, then per round of NB blocks form the lag moments
+// (phase 1) and combine them per point (phase 2). Adds the step's C into (cr, ci).
+template <bool kRound, int Q>
+__device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
+                          const FactStep& st, float2* s_y, float2* s_v, float2* s_G, const float2* s_rot, float& cr,
+                          float& ci) {
+    const int tid = threadIdx.x;
+    const double centre = 0.5 * (double)(a.L - 1);
+    const int Hs = st.Hs;
+    for (int s0 = 0; s0 < a.L; s0 += st.TB * kFB) {
+        const int tl = min(st.TB * kFB, a.L - s0);
+        const int nblk = (tl + kFB - 1) / kFB;
+        __syncthreads();
+        {
+            const int64_t m0 = st.n_step + s0 + st.dlo;
+            const int len = nblk * kFB + Hs;
+            for (int t = tid; t < len; t += 256) {
+                const int64_t m = m0 + t;
+                s_y[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
             }
+            for (int t = tid; t < nblk * kFB; t += 256) {
+                float2 v = make_float2(0.f, 0.f);
+                if (t < tl) {
+                    const float2 x = yi[st.n_step + s0 + t];
+                    const float2 rt = s_rot[t & (kFB - 1)];
+                    v = make_float2(x.x * rt.x - x.y * rt.y, x.x * rt.y + x.y * rt.x);
+                }
+                s_v[(t >> 6) * kFVS + (t & (kFB - 1))] = v;
+            }
+        }
+        __syncthreads();
+        float2 W = cis_cycles(st.cyc * ((double)s0 + 0.5 * (double)(kFB - 1) - centre));
+        for (int bb = 0; bb < nblk; bb += st.NB) {
+            // phase 1: item (my_b, my_l) forms the moments of block bb + my_b at lags my_l, my_l + 1
+            const int b = bb + st.my_b;
+            if (st.my_b < st.NB && b < nblk) {
+                float2 G0[Q], G1[Q];
+                block_moments2<Q>(s_v + b * kFVS, s_y + b * kFB + st.my_l, G0, G1);
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    *reinterpret_cast<float4*>(s_G + (st.my_b * Q + q) * Hs + st.my_l) =
+                        make_float4(G0[q].x, G0[q].y, G1[q].x, G1[q].y);
+            }
+            __syncthreads();
+            // phase 2: every point combines 2Q moments per block
+            const int nb = min(st.NB, nblk - bb);
+            for (int w = 0; w < nb; ++w) {
+                const float2* g = s_G + w * Q * Hs + st.off;
+                float m[Q][2];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const float2 g0 = g[q * Hs];
+                    m[q][0] = g0.x;
+                    m[q][1] = g0.y;
+                    if constexpr (!kRound) {
+                        const float2 g1 = g[q * Hs + 1];
+                        m[q][0] = fmaf(st.alpha, g1.x - g0.x, g0.x);
+                        m[q][1] = fmaf(st.alpha, g1.y - g0.y, g0.y);
+                    }
+                }
+                // s = m0 + j c1 m1 + c2 m2 + j c3 m3
+                float sr = m[0][0], si = m[0][1];
+                if constexpr (Q > 1) {
+                    sr = fmaf(-st.c1, m[1][1], sr);
+                    si = fmaf(st.c1, m[1][0], si);
+                }
+                if constexpr (Q > 2) {
+                    sr = fmaf(st.c2, m[2][0], sr);
+                    si = fmaf(st.c2, m[2][1], si);
+                }
+                if constexpr (Q > 3) {
+                    sr = fmaf(-st.c3, m[3][1], sr);
+                    si = fmaf(st.c3, m[3][0], si);
+                }
+                cr = fmaf(W.x, sr, fmaf(-W.y, si, cr));
+                ci = fmaf(W.x, si, fmaf(W.y, sr, ci));
+                const float wr = fmaf(W.x, st.ERB.x, -(W.y * st.ERB.y));
+                W.y = fmaf(W.x, st.ERB.y, W.y * st.ERB.x);
+                W.x = wr;
+            }
+            __syncthreads();
         }
     }
 }
 
 template <bool kRound>
 __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
-    __shared__ float2 s_y[kFT + kFH + 2];
-    __shared__ float2 s_v[kFT];
-    __shared__ float2 s_G[kFQ * 256];          // [round block][q][lag], at most 256 (block, lag) items
+    __shared__ float2 s_y[kFT + kFH + 4];
+    __shared__ float2 s_v[kFTB * kFVS];
+    __shared__ __align__(16) float2 s_G[kFQ * 512];   // [round block][q][lag], <= 512 (block, lag) slots
     __shared__ float2 s_rot[kFB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
@@ -111,7 +217,6 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
     bool valid;
     const int64_t p = tile_point(a.tiling, tile, tid, &valid);
     double jacc = (valid && a.load_J && a.n_groups == 1) ? (double)a.J[p] : 0.0;
-    const double centre = 0.5 * (double)(a.L - 1);
     const double two_pi = 6.283185307179586476925;
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
@@ -120,147 +225,77 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
-        {
-            const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
-            double D = valid ? a.D[gi] : 0.0;
-            const double nu = valid ? a.nu[gi] : 0.0;
-            if (!(fabs(D) < 1.0e9)) D = 1.0e9;
-            int d0;
-            float alpha;
-            if constexpr (kRound) {
-                d0 = (int)round(D);
-                alpha = 0.f;
-            } else {
-                const double f = floor(D);
-                d0 = (int)f;
-                alpha = (float)(D - f);
-            }
-            const double cyc = nu * a.inv_fs;             // cycles per sample
-            const float th = (float)(two_pi * cyc);       // radians per sample
-            int dlo = valid ? d0 : INT_MAX, dhi = valid ? d0 : INT_MIN;
-            float tlo = valid ? th : FLT_MAX, thi = valid ? th : -FLT_MAX;
-            wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
-            const int64_t spread = (int64_t)dhi - (int64_t)dlo;
-            const float tbar = 0.5f * (tlo + thi);
-            const float xr = 0.5f * (thi - tlo) * (0.5f * kFB);
-            // smallest Q with (delta_max * 32)^Q / Q! <= tol (uniform over the workgroup)
-            int Q = 0;
-            if (xr == xr && xr < 1.f) {
-                float term = 1.f;
-                for (int q = 1; q <= kFQ; ++q) {
-                    term *= xr / q;
-                    if (term <= kFTol) {
-                        Q = q;
-                        break;
-                    }
-                }
-            }
-            const bool fact = Q > 0 && spread + 2 <= kFH;
-            if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
-            if (!fact) continue;                           // uniform: the per-point kernel takes it
-
-            const int H = (int)spread + 2;
-            const int NB = min(kFTB, 256 / H);            // blocks per round
-            const int TB = NB * (kFTB / NB);              // blocks per LDS tile (whole rounds)
-            const int my_b = tid / H;                     // this thread's (block, lag) item
-            const int my_l = tid - my_b * H;
-            const int off = valid ? d0 - dlo : 0;
-            // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
-            const float dl = (float)(two_pi * cyc - (double)tbar);
-            const float c1 = dl, c2 = -0.5f * dl * dl, c3 = -dl * dl * dl * (1.f / 6.f);
-            const float2 ERB = cis_cycles(cyc * (double)kFB);
-            if (tid < kFB) {
-                float s, c;
-                sincosf(tbar * ((float)tid - 0.5f * (float)(kFB - 1)), &s, &c);
-                s_rot[tid] = make_float2(c, s);
-            }
-            float cr = 0.f, ci = 0.f;
-            for (int s0 = 0; s0 < a.L; s0 += TB * kFB) {
-                const int tl = min(TB * kFB, a.L - s0);
-                const int nblk = (tl + kFB - 1) / kFB;
-                __syncthreads();
-                {
-                    const int64_t m0 = n_step + s0 + dlo;
-                    const int len = nblk * kFB + H;
-                    for (int t = tid; t < len; t += 256) {
-                        const int64_t m = m0 + t;
-                        s_y[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
-                    }
-                    for (int t = tid; t < nblk * kFB; t += 256) {
-                        float2 v = make_float2(0.f, 0.f);
-                        if (t < tl) {
-                            const float2 x = yi[n_step + s0 + t];
-                            const float2 rt = s_rot[t & (kFB - 1)];
-                            v = make_float2(x.x * rt.x - x.y * rt.y, x.x * rt.y + x.y * rt.x);
-                        }
-                        s_v[t] = v;
-                    }
-                }
-                __syncthreads();
-                float2 W = cis_cycles(cyc * ((double)s0 + 0.5 * (double)(kFB - 1) - centre));
-                for (int bb = 0; bb < nblk; bb += NB) {
-                    // phase 1: item (my_b, my_l) forms the moments of block bb + my_b at lag my_l
-                    const int b = bb + my_b;
-                    if (my_b < NB && b < nblk) {
-                        float2 G[kFQ];
-                        const float2* v = s_v + b * kFB;
-                        const float2* y = s_y + b * kFB + my_l;
-                        switch (Q) {
-                            case 1: block_moments<1>(v, y, G); break;
-                            case 2: block_moments<2>(v, y, G); break;
-                            case 3: block_moments<3>(v, y, G); break;
-                            default: block_moments<4>(v, y, G); break;
-                        }
-#pragma unroll
-                        for (int q = 0; q < kFQ; ++q)
-                            if (q < Q) s_G[(my_b * Q + q) * H + my_l] = G[q];
-                    }
-                    __syncthreads();
-                    // phase 2: every point combines 2Q moments per block
-                    const int nb = min(NB, nblk - bb);
-                    for (int w = 0; w < nb; ++w) {
-                        const float2* g = s_G + w * Q * H + off;
-                        float m[kFQ][2];
-#pragma unroll
-                        for (int q = 0; q < kFQ; ++q) {
-                            if (q < Q) {
-                                const float2 g0 = g[q * H];
-                                m[q][0] = g0.x;
-                                m[q][1] = g0.y;
-                                if constexpr (!kRound) {
-                                    const float2 g1 = g[q * H + 1];
-                                    m[q][0] = fmaf(alpha, g1.x - g0.x, g0.x);
-                                    m[q][1] = fmaf(alpha, g1.y - g0.y, g0.y);
-                                }
-                            }
-                        }
-                        // s = m0 + j c1 m1 + c2 m2 + j c3 m3
-                        float sr = m[0][0], si = m[0][1];
-                        if (Q > 1) {
-                            sr = fmaf(-c1, m[1][1], sr);
-                            si = fmaf(c1, m[1][0], si);
-                        }
-                        if (Q > 2) {
-                            sr = fmaf(c2, m[2][0], sr);
-                            si = fmaf(c2, m[2][1], si);
-                        }
-                        if (Q > 3) {
-                            sr = fmaf(-c3, m[3][1], sr);
-                            si = fmaf(c3, m[3][0], si);
-                        }
-                        cr = fmaf(W.x, sr, fmaf(-W.y, si, cr));
-                        ci = fmaf(W.x, si, fmaf(W.y, sr, ci));
-                        const float wr = fmaf(W.x, ERB.x, -(W.y * ERB.y));
-                        W.y = fmaf(W.x, ERB.y, W.y * ERB.x);
-                        W.x = wr;
-                    }
-                    __syncthreads();
-                }
-            }
-            const double pw = (double)cr * cr + (double)ci * ci;
-            jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
+        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
+        double D = valid ? a.D[gi] : 0.0;
+        const double nu = valid ? a.nu[gi] : 0.0;
+        if (!(fabs(D) < 1.0e9)) D = 1.0e9;
+        int d0;
+        float alpha;
+        if constexpr (kRound) {
+            d0 = (int)round(D);
+            alpha = 0.f;
+        } else {
+            const double f = floor(D);
+            d0 = (int)f;
+            alpha = (float)(D - f);
         }
+        const double cyc = nu * a.inv_fs;             // cycles per sample
+        const float th = (float)(two_pi * cyc);       // radians per sample
+        int dlo = valid ? d0 : INT_MAX, dhi = valid ? d0 : INT_MIN;
+        float tlo = valid ? th : FLT_MAX, thi = valid ? th : -FLT_MAX;
+        wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
+        const int64_t spread = (int64_t)dhi - (int64_t)dlo;
+        const float tbar = 0.5f * (tlo + thi);
+        const float xr = 0.5f * (thi - tlo) * (0.5f * kFB);
+        // smallest Q with (delta_max * 32)^Q / Q! <= tol (uniform over the workgroup)
+        int Q = 0;
+        if (xr == xr && xr < 1.f) {
+            float term = 1.f;
+            for (int q = 1; q <= kFQ; ++q) {
+                term *= xr / q;
+                if (term <= kFTol) {
+                    Q = q;
+                    break;
+                }
+            }
+        }
+        const bool fact = Q > 0 && spread + 2 <= kFH;
+        if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
+        if (!fact) continue;                           // uniform: the per-point kernel takes it
+
+        FactStep st;
+        const int H = (int)spread + 2;
+        const int Hg = (H + 1) / 2;                    // lag pairs
+        st.n_step = (int64_t)(a.k0 + kk) * a.L;
+        st.cyc = cyc;
+        st.ERB = cis_cycles(cyc * (double)kFB);
+        st.alpha = alpha;
+        // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
+        const float dl = (float)(two_pi * cyc - (double)tbar);
+        st.c1 = dl;
+        st.c2 = -0.5f * dl * dl;
+        st.c3 = -dl * dl * dl * (1.f / 6.f);
+        st.dlo = dlo;
+        st.Hs = 2 * Hg;
+        st.NB = min(kFTB, 256 / Hg);
+        st.TB = st.NB * (kFTB / st.NB);
+        st.my_b = tid / Hg;
+        st.my_l = 2 * (tid - st.my_b * Hg);
+        st.off = valid ? d0 - dlo : 0;
+        if (tid < kFB) {
+            float sn, cs;
+            sincosf(tbar * ((float)tid - 0.5f * (float)(kFB - 1)), &sn, &cs);
+            s_rot[tid] = make_float2(cs, sn);
+        }
+        float cr = 0.f, ci = 0.f;
+        switch (Q) {
+            case 1: fact_step<kRound, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 2: fact_step<kRound, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kRound, 3>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kRound, 4>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+        }
+        const double pw = (double)cr * cr + (double)ci * ci;
+        jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
     }
     if (!valid) return;
     if (a.n_groups == 1)
