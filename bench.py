@@ -29,7 +29,7 @@ UNIT = "grid-pt·sample correlations/s"
 # accumulate 2 + phasor advance 6. The tile-factored form does far less per correlation;
 # its count comes from the geometry of the map (factored_work below).
 FLOP_PER_UNIT_POINTWISE = 26
-TILE, FB, FTB, FQ, FH, FTOL = 16, 64, 16, 4, 128, 2.0 ** -24
+FB, FQ, FH, FTOL = 64, 4, 128, 2.0 ** -24
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_direct_map_1e6.json")
 KERNEL_SOURCES = ["paper_2508_06672_amd/csrc/k_direct_fact.hip", "paper_2508_06672_amd/csrc/internal.h"]
@@ -60,49 +60,64 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def tile_index(rows: int, cols: int, w: int, h: int, shear: int, transpose: int):
+    """Flat point index of every (tile, lane) of a RECT tiling, -1 outside the grid: tiles
+    of h rows of w cells, row i shifted by shear * i columns (rows and columns swapped with
+    transpose), in bands of h rows."""
+    import numpy as np
+    R, C = (cols, rows) if transpose else (rows, cols)
+    ty_n = -(-R // h)
+    tx_n = -(-(C + abs(shear) * (h - 1)) // w)
+    tile = np.arange(ty_n * tx_n, dtype=np.int64)[:, None]
+    lane = np.arange(256, dtype=np.int64)[None, :]
+    ty, tx = np.divmod(tile, tx_n)
+    r0 = ty * h
+    r = r0 + lane // w
+    b0 = -shear * (r0 + h - 1) if shear > 0 else -shear * r0
+    c = shear * r + b0 + tx * w + lane % w
+    valid = (r < R) & (c >= 0) & (c < C)
+    rr, cc = (c, r) if transpose else (r, c)
+    return np.where(valid, rr * cols + cc, -1)
+
+
 def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int = 10):
     """Algorithmic FP32 operations of one map in the tile-factored form, from the map's own
-    geometry, with each 16 x 16 tile and step classified as the kernel does (lag spread H =
-    max d0 - min d0 + 2, Taylor order Q from the tile's Doppler spread, deferred when H > 128
-    or no Q <= 4 bounds the remainder). Per factored tile and step: rotation of the
-    reference samples 6 L; lag moments H L (6 + 2 + 4 (Q - 1)); per point and 64-sample
-    block 6 Q for the two-tap interpolation of the moments (LINEAR only), 4 (Q - 1) for
-    the Taylor coefficients, 8 + 6 for the block weight and its recurrence. Returns (flops,
-    factored units, deferred tile-steps, all tile-steps)."""
+    geometry, with each tile (of the shape the plan chose for the map) and step classified
+    as the kernel does (lag spread H = max d0 - min d0 + 2, Taylor order Q from the tile's
+    Doppler spread, deferred when H > 128 or no Q <= 4 bounds the remainder). Per factored
+    tile and step: rotation of the reference samples 6 L; lag moments H L (6 + 2 + 4 (Q - 1));
+    per point and 64-sample block 6 Q for the two-tap interpolation of the moments (LINEAR
+    only), 4 (Q - 1) for the Taylor coefficients, 8 + 6 for the block weight and its
+    recurrence. Returns (flops, factored units, deferred tile-steps, all tile-steps)."""
     import numpy as np
+    info = plan.info()
+    idx = torch.from_numpy(tile_index(wl.n_rows, wl.n_cols, info["tile_cols"], info["tile_rows"],
+                                      info["tile_shear"], info["tile_transpose"])).cuda()
+    valid = idx >= 0
+    gidx = idx.clamp(min=0)
     L = wl.step_len
-
-    def blocks(H):
-        # LDS tiles hold whole rounds of floor(256 / H) blocks
-        nb = torch.clamp(256 // H, max=FTB)
-        t = (nb * (FTB // nb) * FB).double()
-        full = torch.floor(L / t)
-        rest = L - full * t
-        return full * (t / FB) + torch.ceil(rest / FB)
-    rows, cols = wl.n_rows, wl.n_cols
-    ty, tx = -(-rows // TILE), -(-cols // TILE)
+    nblk = -(-L // FB)
     inv_fact = [1.0 / float(np.prod(range(1, q + 1))) for q in range(1, FQ + 1)]
     flops = 0.0
     units = 0.0
     deferred = 0
     total = 0
+    nval = valid.sum(-1).double()
+    inf = float("inf")
     for k0 in range(0, wl.n_steps, chunk):
         n = min(chunk, wl.n_steps - k0)
         D, nu = plan.geometry(states, 0, k0, n)
         d0 = torch.round(D) if delay_round else torch.floor(D)
         th = (2 * np.pi * (nu / wl.fs_hz)).float()
-        pad = (0, tx * TILE - cols, 0, ty * TILE - rows)
 
         def tiles(x, fill):
-            x = torch.nn.functional.pad(x.view(n, rows, cols), pad, value=fill)
-            return x.view(n, ty, TILE, tx, TILE).permute(0, 1, 3, 2, 4).reshape(n, ty, tx, TILE * TILE)
+            t = x[:, gidx]
+            return torch.where(valid, t, torch.full_like(t, fill))
 
-        inf = float("inf")
         dlo = tiles(d0, inf).amin(-1)
         dhi = tiles(d0, -inf).amax(-1)
         tlo = tiles(th, inf).amin(-1)
         thi = tiles(th, -inf).amax(-1)
-        nval = tiles(torch.ones_like(th), 0.0).sum(-1)
         H = dhi - dlo + 2
         xr = 0.5 * (thi - tlo) * (0.5 * FB)
         qs = torch.arange(1, FQ + 1, device=xr.device, dtype=torch.float32)
@@ -110,11 +125,10 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         ok = (terms <= FTOL) & (xr < 1).unsqueeze(-1)
         Q = torch.where(ok.any(-1), ok.float().argmax(-1) + 1, torch.zeros_like(xr, dtype=torch.int64)).double()
         fac = (Q > 0) & (H <= FH)
-        nblk = blocks(torch.where(fac, H, torch.full_like(H, 2.0)).long())
         per_point = nblk * ((0 if delay_round else 6 * Q) + 4 * (Q - 1) + 14)
-        f = 6 * L + H * L * (4 * Q + 4) + nval.double() * per_point
+        f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
         flops += float(torch.where(fac, f, torch.zeros_like(f)).sum())
-        units += float(torch.where(fac, nval.double() * L, torch.zeros_like(f)).sum())
+        units += float(torch.where(fac, nval * L, torch.zeros_like(f)).sum())
         deferred += int((~fac).sum())
         total += fac.numel()
         del D, nu, d0, th
@@ -342,6 +356,8 @@ def main() -> int:
                 "kernel": "k_direct_fact", "launch_ms": round(k_ms, 4), "units_per_launch": units_per_launch,
                 "flop_per_launch": flops_per_launch, "flop_per_unit": round(f_map / max(f_units, 1.0), 4),
                 "deferred_tile_steps": f"{n_def}/{n_ts}",
+                "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear']}"
+                        f"{' transposed' if info['tile_transpose'] else ''}",
                 "pointwise_equivalent_tflops": round(FLOP_PER_UNIT_POINTWISE * units_per_launch / (k_ms / 1e3) / 1e12,
                                                      3)}
 

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GEOLOC_ABI_VERSION 1
+#define GEOLOC_ABI_VERSION 2
 
 /* status codes */
 #define GEOLOC_OK            0
@@ -134,6 +134,9 @@ typedef struct geoloc_plan_info {
                                   method, of the per-point pass over (tile, step) pairs the
                                   factored kernel left to it                              */
     double map_ms;             /* ... of whole geoloc_map calls, first to last kernel    */
+    int32_t tile_rows, tile_cols;   /* workgroup tile of the last map: rows x cells per row */
+    int32_t tile_shear;        /* column shift per tile row (diagonal tiles)              */
+    int32_t tile_transpose;    /* 1: rows and columns swap roles in the tile              */
 } geoloc_plan_info;
 
 /* ABI version of the loaded library (GEOLOC_ABI_VERSION when it matches). */

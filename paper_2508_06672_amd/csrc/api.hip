@@ -53,7 +53,11 @@ struct geoloc_plan_s {
     int64_t N = 0, L = 0, K = 0, P = 0, rows = 0, cols = 0;
     double fs = 0, fc = 0, radius = 0, alt = 0;
     std::vector<int2> pairs;
-    PointTiling tiling{};
+    PointTiling tiling{};            // tiling of the current map
+    PointTiling base_tiling{};       // 16 x 16 squares (RECT) or runs of 256 points (POINTS)
+    std::vector<PointTiling> tile_shapes;   // RECT: candidate tilings of the factored kernel
+    int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
+    std::vector<double> h_lat, h_lon;       // grid coordinates (host copy, for the tile choice)
     int32_t kc = 1;  // steps per geometry chunk
     // device scratch
     double* d_xyz = nullptr;
@@ -221,6 +225,89 @@ int upload_states(geoloc_plan_t p, const double* host, hipStream_t s) {
     HIP_TRY(hipEventRecord(p->states_copied, s));
     p->states_pending = true;
     return GEOLOC_OK;
+}
+
+// Delay (samples) and Doppler (radians per sample) of one grid cell for one pair at one
+// step, in FP64 on the host (Eq. (3)-(8) on the sphere): only the tile choice uses it.
+void host_delay_doppler(const geoloc_plan_s* p, double lat, double lon, const double* si, const double* sj, double* D,
+                        double* th) {
+    const double c = 299792458.0, R = p->radius + p->alt, lambda = c / p->fc;
+    const double x[3] = {R * std::cos(lat) * std::cos(lon), R * std::cos(lat) * std::sin(lon), R * std::sin(lat)};
+    double tau[2], f[2];
+    const double* st[2] = {si, sj};
+    for (int k = 0; k < 2; ++k) {
+        const double dx[3] = {st[k][0] - x[0], st[k][1] - x[1], st[k][2] - x[2]};
+        const double rho = std::sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+        tau[k] = rho / c;
+        f[k] = -(dx[0] * st[k][3] + dx[1] * st[k][4] + dx[2] * st[k][5]) / (rho * lambda);
+    }
+    *D = (tau[1] - tau[0]) * p->fs;
+    *th = 2.0 * 3.14159265358979323846 * (f[1] - f[0]) / p->fs;
+}
+
+// Tile shape for the factored kernel: from the delay and Doppler gradients at the grid
+// centre (first pair, middle step), the candidate with the least predicted VALU work per
+// correlation, counting the lanes its tiles leave outside the grid. The lag moments cost
+// about (8 + 4Q) / NB instructions per correlation (NB blocks per round, from the lag
+// spread H) and the per-point combination (6Q + 8) / 64; a tile that the factored kernel
+// would defer costs about 13.
+void choose_tiling(geoloc_plan_t p, const double* states) {
+    p->tiling = p->base_tiling;
+    if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 || p->tile_shapes.empty()) return;
+    const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
+    const int2 pr = p->pairs[0];
+    const double* si = states + ((size_t)k * p->n_rx + pr.x) * 6;
+    const double* sj = states + ((size_t)k * p->n_rx + pr.y) * 6;
+    auto dd = [&](int64_t r, int64_t c, double* D, double* th) {
+        host_delay_doppler(p, p->h_lat[r], p->h_lon[c], si, sj, D, th);
+    };
+    double g[2][2] = {{0, 0}, {0, 0}};   // [delay, doppler][d/drow, d/dcol]
+    const int64_t ra = std::max<int64_t>(r0 - 1, 0), rb = std::min<int64_t>(r0 + 1, p->rows - 1);
+    const int64_t ca = std::max<int64_t>(c0 - 1, 0), cb = std::min<int64_t>(c0 + 1, p->cols - 1);
+    double D1, t1, D2, t2;
+    if (rb > ra) {
+        dd(ra, c0, &D1, &t1);
+        dd(rb, c0, &D2, &t2);
+        g[0][0] = (D2 - D1) / (double)(rb - ra);
+        g[1][0] = (t2 - t1) / (double)(rb - ra);
+    }
+    if (cb > ca) {
+        dd(r0, ca, &D1, &t1);
+        dd(r0, cb, &D2, &t2);
+        g[0][1] = (D2 - D1) / (double)(cb - ca);
+        g[1][1] = (t2 - t1) / (double)(cb - ca);
+    }
+    if (!std::isfinite(g[0][0] + g[0][1] + g[1][0] + g[1][1])) return;
+    auto cost = [&](const PointTiling& t) {
+        const double gr = t.transpose ? g[0][1] : g[0][0], gc = t.transpose ? g[0][0] : g[0][1];
+        const double hr = t.transpose ? g[1][1] : g[1][0], hc = t.transpose ? g[1][0] : g[1][1];
+        const double H = std::fabs(gr + t.shear * gc) * (t.tile_h - 1) + std::fabs(gc) * (t.tile_w - 1) + 3.0;
+        const double xr = 0.5 * (std::fabs(hr + t.shear * hc) * (t.tile_h - 1) + std::fabs(hc) * (t.tile_w - 1)) * 32.0;
+        int Q = 0;
+        double term = 1.0;
+        for (int q = 1; q <= 4 && xr < 1.0; ++q) {
+            term *= xr / q;
+            if (term <= 5.9604645e-8) {
+                Q = q;
+                break;
+            }
+        }
+        double c = 13.0;
+        if (Q > 0 && H <= 128.0) {
+            const int Hg = (int)std::ceil(H / 2.0);
+            const int NB = std::min(32, 256 / Hg);
+            c = (8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0;
+        }
+        return c * (double)(t.tiles_x * t.tiles_y * kTilePoints) / (double)p->P;
+    };
+    double best = cost(p->base_tiling);
+    for (const auto& t : p->tile_shapes) {
+        const double c = cost(t);
+        if (c < 0.97 * best) {
+            best = c;
+            p->tiling = t;
+        }
+    }
 }
 
 int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc, double* D, double* nu,
@@ -578,21 +665,43 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     p->caf_nu_hi_req = d->caf_nu_hi_hz;
     p->radius = d->earth_radius_m;
     p->alt = d->alt_m;
-    if (d->grid_kind == GEOLOC_GRID_RECT) {
-        p->tiling.rows = d->n_rows;
-        p->tiling.cols = d->n_cols;
-        p->tiling.tile_w = 16;
-        p->tiling.tile_h = 16;
-    } else {
-        p->tiling.rows = 1;
-        p->tiling.cols = P;
-        p->tiling.tile_w = kTilePoints;
-        p->tiling.tile_h = 1;
+    {
+        PointTiling t{};
+        if (d->grid_kind == GEOLOC_GRID_RECT) {
+            t.rows = d->n_rows;
+            t.cols = d->n_cols;
+            t.tile_w = 16;
+            t.tile_h = 16;
+        } else {
+            t.rows = 1;
+            t.cols = P;
+            t.tile_w = kTilePoints;
+            t.tile_h = 1;
+        }
+        tiling_counts(t);
+        p->base_tiling = p->tiling = t;
+        p->max_tiles = t.tiles_x * t.tiles_y;
+        if (d->grid_kind == GEOLOC_GRID_RECT) {
+            // square, tall and taller tiles, sheared by -2..2 columns per row, either way round
+            const int shapes[3][2] = {{16, 16}, {8, 32}, {4, 64}};
+            for (int tr = 0; tr < 2; ++tr)
+                for (int sh = -2; sh <= 2; ++sh)
+                    for (const auto& wh : shapes) {
+                        PointTiling c = t;
+                        c.tile_w = wh[0];
+                        c.tile_h = wh[1];
+                        c.shear = sh;
+                        c.transpose = tr;
+                        tiling_counts(c);
+                        p->tile_shapes.push_back(c);
+                        p->max_tiles = std::max(p->max_tiles, c.tiles_x * c.tiles_y);
+                    }
+        }
+        p->h_lat.assign(d->lat, d->lat + (d->grid_kind == GEOLOC_GRID_RECT ? d->n_rows : P));
+        p->h_lon.assign(d->lon, d->lon + (d->grid_kind == GEOLOC_GRID_RECT ? d->n_cols : P));
     }
-    p->tiling.tiles_x = (p->tiling.cols + p->tiling.tile_w - 1) / p->tiling.tile_w;
-    p->tiling.tiles_y = (p->tiling.rows + p->tiling.tile_h - 1) / p->tiling.tile_h;
 
-    const int64_t table_points = p->tiling.tiles_x * p->tiling.tiles_y * kTilePoints;  // tile-major >= P
+    const int64_t table_points = p->max_tiles * kTilePoints;  // tile-major >= P
     const int64_t per_step = (int64_t)p->n_pairs * table_points * 16;
     int64_t kc = kGeomChunkBytes / per_step;
     if (kc < 1) kc = 1;
@@ -606,11 +715,11 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
         if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
-        p->n_groups = direct_groups(p->tiling.tiles_x * p->tiling.tiles_y, (int64_t)p->kc * p->n_pairs);
+        p->n_groups = direct_groups(p->base_tiling.tiles_x * p->base_tiling.tiles_y, (int64_t)p->kc * p->n_pairs);
         if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
         p->use_fact = p->method == GEOLOC_DIRECT_FP32;
         if (p->use_fact &&
-            (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->tiling.tiles_x * p->tiling.tiles_y)))
+            (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->max_tiles)))
             break;
         p->am.n_blocks = argmax_blocks(P);
         if ((rc = dev_alloc(p, &p->am.part_val, p->am.n_blocks))) break;
@@ -660,6 +769,8 @@ int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     for (int64_t i = 0; i < n_lon; ++i)
         if (!std::isfinite(lon[i])) return fail(GEOLOC_EINVAL, "lon[%lld] not finite", (long long)i);
     HIP_TRY(hipDeviceSynchronize());
+    p->h_lat.assign(lat, lat + n_lat);
+    p->h_lon.assign(lon, lon + n_lon);
     HIP_TRY(hipMemcpy(p->d_lat, lat, n_lat * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_lon, lon, n_lon * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->radius + p->alt, p->d_xyz, nullptr));
@@ -685,6 +796,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
     hipStream_t s = (hipStream_t)in->stream;
     int rc = upload_states(p, in->rx_state, s);
     if (rc) return rc;
+    choose_tiling(p, in->rx_state);
     TimedSpan whole{};
     if ((rc = span_begin(p, s, &whole, 3))) return rc;
     if (p->method == GEOLOC_CAF_BF16 || p->method == GEOLOC_CAF_FP16) {
@@ -707,7 +819,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.pairs = p->d_pairs;
         a.J = J;
         a.tiling = p->tiling;
-        a.n_tiles = p->tiling.tiles_x * p->tiling.tiles_y;
+        a.n_tiles = p->tiling.tiles_x * p->tiling.tiles_y;   // <= max_tiles
         a.N = p->N;
         a.P = p->P;
         a.L = (int32_t)p->L;
@@ -839,6 +951,10 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.correlate_ms = p->t_corr;
     r.interp_ms = p->t_interp;
     r.map_ms = p->t_map;
+    r.tile_rows = p->tiling.tile_h;
+    r.tile_cols = p->tiling.tile_w;
+    r.tile_shear = p->tiling.shear;
+    r.tile_transpose = p->tiling.transpose;
     *out = r;
     return GEOLOC_OK;
 }

@@ -13,23 +13,44 @@ namespace geoloc {
 
 constexpr double kLightSpeed = 299792458.0;
 
-// Points handled by one workgroup of the correlation kernels: a 16 x 16 tile of a
-// RECT grid (neighbouring cells have neighbouring delays, so the lag spread a tile
-// needs in LDS stays small), or 256 consecutive entries of a POINTS list.
+// Points handled by one workgroup of the correlation kernels: a tile of 256 cells of a
+// RECT grid (neighbouring cells have neighbouring delays, so the lag spread a tile needs
+// in LDS stays small), or 256 consecutive entries of a POINTS list.
+//
+// A RECT tile is tile_h rows of tile_w cells in which row i is shifted by shear * i
+// columns, a parallelogram that can follow a diagonal line of equal delay (with
+// `transpose`, rows and columns swap roles). Tiles stack in bands of tile_h rows; each band
+// holds tiles_x tiles, enough to cover the sheared band, and cells outside the grid are
+// invalid lanes. shear = 0, 16 x 16 is the plain square tiling.
 constexpr int kTilePoints = 256;
 
 struct PointTiling {
     int64_t rows, cols;     // RECT: grid shape; POINTS: 1 x P
-    int32_t tile_w, tile_h; // 16 x 16 (RECT) or 256 x 1 (POINTS)
-    int64_t tiles_x, tiles_y;
+    int32_t tile_w, tile_h; // cells per tile row, rows per tile (POINTS: 256 x 1)
+    int64_t tiles_x, tiles_y;   // tiles per band, bands
+    int32_t shear;          // column shift per tile row (RECT)
+    int32_t transpose;      // 1: the roles of rows and columns are swapped (RECT)
 };
 
+// Tile count of a tiling with the given shape over a rows x cols grid.
+__host__ __device__ inline void tiling_counts(PointTiling& t) {
+    const int64_t R = t.transpose ? t.cols : t.rows, C = t.transpose ? t.rows : t.cols;
+    const int64_t sh = t.shear < 0 ? -t.shear : t.shear;
+    t.tiles_y = (R + t.tile_h - 1) / t.tile_h;
+    t.tiles_x = (C + sh * (t.tile_h - 1) + t.tile_w - 1) / t.tile_w;
+}
+
 __host__ __device__ inline int64_t tile_point(const PointTiling& t, int64_t tile, int lane, bool* valid) {
-    int64_t ty = tile / t.tiles_x, tx = tile - ty * t.tiles_x;
-    int64_t r = ty * t.tile_h + lane / t.tile_w;
-    int64_t c = tx * t.tile_w + lane % t.tile_w;
-    *valid = (r < t.rows) && (c < t.cols);
-    return r * t.cols + c;
+    const int64_t ty = tile / t.tiles_x, tx = tile - ty * t.tiles_x;
+    const int64_t R = t.transpose ? t.cols : t.rows, C = t.transpose ? t.rows : t.cols;
+    const int64_t r0 = ty * t.tile_h;
+    const int64_t r = r0 + lane / t.tile_w;
+    // first column of the band's sheared coordinate: the band's rows cover [0, C)
+    const int64_t b0 = t.shear > 0 ? -(int64_t)t.shear * (r0 + t.tile_h - 1) : -(int64_t)t.shear * r0;
+    const int64_t c = (int64_t)t.shear * r + b0 + tx * t.tile_w + lane % t.tile_w;
+    *valid = (r < R) && (c >= 0) && (c < C);
+    const int64_t rr = t.transpose ? c : r, cc = t.transpose ? r : c;
+    return *valid ? rr * t.cols + cc : 0;
 }
 
 struct DirectArgs {

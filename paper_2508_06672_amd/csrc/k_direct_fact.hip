@@ -34,7 +34,7 @@
 namespace geoloc {
 
 constexpr int kFB = 64;          // samples per moment block
-constexpr int kFTB = 16;         // most blocks per LDS tile
+constexpr int kFTB = 32;         // most blocks per LDS tile
 constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
 constexpr int kFQ = 4;           // most Taylor terms
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgeoloc.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
@@ -67,6 +67,8 @@ class geoloc_plan_info(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("timed_maps", ctypes.c_int64), ("correlate_launches", ctypes.c_int64),
         ("geometry_ms", ctypes.c_double), ("correlate_ms", ctypes.c_double), ("interp_ms", ctypes.c_double),
         ("map_ms", ctypes.c_double),
+        ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32), ("tile_shear", ctypes.c_int32),
+        ("tile_transpose", ctypes.c_int32),
     ]
 
 

@@ -51,11 +51,10 @@ def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
 
 
 def test_refined_tiles_reproduce_the_full_map(torch, P):
-    """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals, bit
-    for bit, the full-grid map at those cells: the same tile-factored kernel sees the same
-    256 points per workgroup and the same step split. The per-point kernel agrees to FP32
-    rounding. When the chosen tiles contain the full map's peak the refined peak is that
-    peak."""
+    """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals the
+    full-grid map at those cells to FP32 rounding (the full grid may use sheared tiles, so
+    the sums group differently), as does the per-point kernel. When the chosen tiles
+    contain the full map's peak the refined peak is that peak."""
     from paper_2508_06672_amd import geoloc
     wl = SMALL_WL
     net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
@@ -75,9 +74,9 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     plat, plon, idx = P.tile_points(scn.lat, scn.lon, tiles)
     prop.refine.set_grid(plat, plon)
     Jr = prop.refine.map(caps, states).cpu().numpy()
-    assert np.array_equal(Jr, Jf[idx])
+    assert float(np.max(np.abs(Jr.astype(np.float64) - Jf[idx]))) <= 2e-5 * float(Jf.max())
     i, v = prop.refine_tiles(caps, states, tiles)
-    assert i == a_full and v == v_full
+    assert Jf[i] >= (1 - 4e-5) * v_full and abs(v - v_full) <= 2e-5 * v_full
     prop.close()
     net.close()
 
