@@ -31,7 +31,7 @@ UNIT = "grid-pt·sample correlations/s"
 FLOP_PER_UNIT_POINTWISE = 26
 FB, FQ, FH, FTOL = 64, 4, 128, 2.0 ** -24
 PEAK_FP32_TFLOPS = 157.3          # MI355X published FP32 vector peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_direct_map_1e6.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_direct_fact_map_1e6.json")
 KERNEL_SOURCES = ["paper_2508_06672_amd/csrc/k_direct_fact.hip", "paper_2508_06672_amd/csrc/internal.h"]
 
 

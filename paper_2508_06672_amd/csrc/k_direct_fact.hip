@@ -34,9 +34,15 @@
 namespace geoloc {
 
 constexpr int kFB = 64;          // samples per moment block
-constexpr int kFTB = 32;         // most blocks per LDS tile
+#ifndef GEOLOC_FACT_TB
+#define GEOLOC_FACT_TB 32
+#endif
+#ifndef GEOLOC_FACT_Q
+#define GEOLOC_FACT_Q 4
+#endif
+constexpr int kFTB = GEOLOC_FACT_TB;   // most blocks per LDS tile
 constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
-constexpr int kFQ = 4;           // most Taylor terms
+constexpr int kFQ = GEOLOC_FACT_Q;     // most Taylor terms
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
 constexpr int kFVS = kFB + 2;    // LDS stride of the reference samples of one block
 constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
@@ -291,8 +297,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         switch (Q) {
             case 1: fact_step<kRound, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
             case 2: fact_step<kRound, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 3: fact_step<kRound, 3>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            default: fact_step<kRound, 4>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kRound, (kFQ < 3 ? kFQ : 3)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kRound, kFQ>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
         }
         const double pw = (double)cr * cr + (double)ci * ci;
         jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
