@@ -124,13 +124,13 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         terms = xr.unsqueeze(-1) ** qs * torch.tensor(inv_fact, dtype=torch.float32, device=xr.device)
         ok = (terms <= FTOL) & (xr < 1).unsqueeze(-1)
         Q = torch.where(ok.any(-1), ok.float().argmax(-1) + 1, torch.zeros_like(xr, dtype=torch.int64)).double()
-        fac = (Q > 0) & (H <= FH)
+        fac = (Q > 0) & (H <= FH) & (nval > 0)     # tiles with no grid cell do no work
         per_point = nblk * ((0 if delay_round else 6 * Q) + 4 * (Q - 1) + 14)
         f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
         flops += float(torch.where(fac, f, torch.zeros_like(f)).sum())
         units += float(torch.where(fac, nval * L, torch.zeros_like(f)).sum())
-        deferred += int((~fac).sum())
-        total += fac.numel()
+        deferred += int((~fac & (nval > 0)).sum())
+        total += int((nval > 0).sum()) * n
         del D, nu, d0, th
     return flops, units, deferred, total
 

@@ -250,6 +250,10 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         int dlo = valid ? d0 : INT_MAX, dhi = valid ? d0 : INT_MIN;
         float tlo = valid ? th : FLT_MAX, thi = valid ? th : -FLT_MAX;
         wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
+        if (dhi < dlo) {                               // no grid cell in this tile: nothing to add
+            if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = 0;
+            continue;
+        }
         const int64_t spread = (int64_t)dhi - (int64_t)dlo;
         const float tbar = 0.5f * (tlo + thi);
         const float xr = 0.5f * (thi - tlo) * (0.5f * kFB);
