@@ -432,8 +432,8 @@ int caf_prepare(geoloc_plan_t p, const float2* cap, hipStream_t s) {
     }
     p->caf_lag_lo = lag_lo;
     p->caf_n_lags = (int32_t)n_lags;
-    p->caf_n_lags_pad = (int32_t)round_up(n_lags, 64);
-    p->caf_M_pad = (int32_t)round_up(M, 256);
+    p->caf_n_lags_pad = (int32_t)round_up(n_lags, kCafTileLags);
+    p->caf_M_pad = (int32_t)round_up(M, kCafTileBins);
     p->caf_L_pad = (int32_t)round_up(p->L, 16);
     p->caf_nu_lo = lo;
     p->caf_nu_hi = hi;
@@ -467,7 +467,7 @@ void caf_split(geoloc_plan_t p, int32_t n_pairs, int64_t n_steps, int32_t* kc_ou
                int32_t* chunk_out) {
     const int64_t per_step = (int64_t)n_pairs * p->caf_n_lags_pad * p->caf_M_pad * 8;
     int64_t kc = std::max<int64_t>(1, std::min<int64_t>(n_steps, kCafTableBytes / per_step));
-    const int64_t wgs = (int64_t)(p->caf_n_lags_pad / 64) * (p->caf_M_pad / 256) * n_pairs * kc;
+    const int64_t wgs = (int64_t)(p->caf_n_lags_pad / kCafTileLags) * (p->caf_M_pad / kCafTileBins) * n_pairs * kc;
     int64_t n_split = 1, chunk = p->L;
     if (wgs < 1024) {
         n_split = std::min<int64_t>((1024 + wgs - 1) / wgs, (p->L + 255) / 256);

@@ -132,6 +132,11 @@ __device__ inline void pair_delay_doppler(const CafGeomArgs& g, int64_t p, int32
     *nu = fj - fi;
 }
 
+// CAF GEMM workgroup tile: table rows (lags) x columns (Doppler bins); the table is padded
+// to whole tiles
+constexpr int kCafTileLags = 128;
+constexpr int kCafTileBins = 128;
+
 struct CafGemmArgs {
     const float2* cap;             // [n_rx][N]
     const int2* pairs;

@@ -27,8 +27,10 @@
 // B[8 (l / 32) + j][l % 32], j < 8; accumulator i of lane l is C[8 (i / 4) + 4 (l / 32) +
 // (i % 4)][l % 32]. Complex product as four real MFMAs:
 //   Tr += Ar Fr + (-Ai) Fi,   Ti += Ar Fi + Ai Fr.
-// A wave owns 32 lags x 128 bins (4 column blocks, 128 FP32 accumulators); a workgroup of
-// 4 waves owns 64 lags x 256 bins.
+// A wave owns 64 lags x 64 bins (2 x 2 blocks of 32 x 32, 128 FP32 accumulators), so that
+// every F fragment it loads feeds two row blocks and every lag-product fragment two column
+// blocks; a workgroup of 4 waves owns 128 lags x 128 bins. Two waves per SIMD (the
+// accumulators then live in VGPRs) let one wave form lag products while another's MFMAs run.
 #include "internal.h"
 
 #include <cfloat>
@@ -40,7 +42,13 @@ typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(unsigned int)))) unsigned int u32x4;
 
-constexpr int kCafKc = 256;  // samples staged in LDS per chunk (multiple of 16)
+#ifndef GEOLOC_CAF_KC
+#define GEOLOC_CAF_KC 256
+#endif
+constexpr int kCafKc = GEOLOC_CAF_KC;  // samples staged in LDS per chunk (multiple of 16)
+#ifndef GEOLOC_CAF_WAVES_PER_EU
+#define GEOLOC_CAF_WAVES_PER_EU 2
+#endif
 
 // --------------------------------------------------------------------------- extent
 
@@ -147,16 +155,19 @@ struct MfmaTypes<true> {
 };
 
 template <bool kF16>
-__global__ __launch_bounds__(256) void k_caf_gemm(CafGemmArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEOLOC_CAF_WAVES_PER_EU))) void k_caf_gemm(CafGemmArgs a) {
     using MT = MfmaTypes<kF16>;
     using vec = typename MT::vec;
     __shared__ float2 s_yi[kCafKc];
-    __shared__ float2 s_yj[kCafKc + 64 + 16];
+    __shared__ float2 s_yj[kCafKc + kCafTileLags + 16];
 
+    // workgroup: 128 lags x 128 bins; wave (wrow, wcol): 64 lags x 64 bins, four 32 x 32
+    // blocks, so that each B fragment of F feeds two row blocks and each A fragment two
+    // column blocks
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wrow = wave >> 1, wcol = wave & 1;
-    const int lag_base = blockIdx.x * 64;              // table row of this workgroup
-    const int bin_base = blockIdx.y * 256 + wcol * 128;
+    const int lag_base = blockIdx.x * kCafTileLags;    // table row of this workgroup
+    const int bin_base = blockIdx.y * kCafTileBins + wcol * 64;
     const int z = blockIdx.z;                          // (split, pair, step)
     const int split = z % a.n_split;
     const int ek = z / a.n_split;                      // pair * kc + step-in-chunk
@@ -169,13 +180,14 @@ __global__ __launch_bounds__(256) void k_caf_gemm(CafGemmArgs a) {
     const int c1 = min(a.L, c0 + a.chunk);
     const int64_t lag0 = (int64_t)a.lag_lo + lag_base; // lag of table row lag_base
 
-    f32x16 tr[4], ti[4];
+    f32x16 tr[2][2], ti[2][2];                         // [row block][column block]
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) tr[cb][i] = ti[cb][i] = 0.f;
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) tr[rb][cb][i] = ti[rb][cb][i] = 0.f;
 
-    const int row = wrow * 32 + (lane & 31);           // row of the workgroup tile
     const int kg = lane >> 5;                          // which 8 samples of the 16-sample K step
 
     for (int s0 = c0; s0 < c1; s0 += kCafKc) {
@@ -190,62 +202,70 @@ __global__ __launch_bounds__(256) void k_caf_gemm(CafGemmArgs a) {
             }
             s_yi[t] = v;
         }
-        for (int t = tid; t < kCafKc + 64 + 16; t += 256) {
+        for (int t = tid; t < kCafKc + kCafTileLags + 16; t += 256) {
             const int64_t m = n_step + s0 + lag0 + t;
             s_yj[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
         }
         __syncthreads();
         const int nks = (len + 15) >> 4;
         for (int ks = 0; ks < nks; ++ks) {
-            // A fragments: lag products of this lane's row at 8 consecutive samples
-            u32x4 par, pai;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                unsigned int wr = 0, wi = 0;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int t = ks * 16 + kg * 8 + 2 * q + h;
-                    const float2 x = s_yi[t];
-                    const float2 y = s_yj[t + row];
-                    const float lr = fmaf(x.x, y.x, x.y * y.y);  // x * conj(y)
-                    const float li = fmaf(x.y, y.x, -(x.x * y.y));
-                    wr |= (unsigned int)MT::cvt(lr) << (16 * h);
-                    wi |= (unsigned int)MT::cvt(li) << (16 * h);
-                }
-                par[q] = wr;
-                pai[q] = wi;
-            }
-            const u32x4 pnai = pai ^ 0x80008000u;   // -Ai: flip both sign bits of each word
-            const vec va = __builtin_bit_cast(vec, par);
-            const vec vai = __builtin_bit_cast(vec, pai);
-            const vec vnai = __builtin_bit_cast(vec, pnai);
-            // B fragments: F at the same 8 samples for bins bin_base + 32 cb + lane % 32
+            // B fragments: F at this lane's 8 samples for bins bin_base + 32 cb + lane % 32
             const int64_t g = (int64_t)((s0 + ks * 16) >> 3) + kg;
+            vec fr[2], fi[2];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
+            for (int cb = 0; cb < 2; ++cb) {
                 const int64_t o = (g * a.M_pad + bin_base + cb * 32 + (lane & 31)) * 8;
-                const u32x4 fr4 = *reinterpret_cast<const u32x4*>(a.Fr + o);
-                const u32x4 fi4 = *reinterpret_cast<const u32x4*>(a.Fi + o);
-                const vec fr = __builtin_bit_cast(vec, fr4);
-                const vec fi = __builtin_bit_cast(vec, fi4);
-                tr[cb] = MT::mfma(va, fr, tr[cb]);
-                tr[cb] = MT::mfma(vnai, fi, tr[cb]);
-                ti[cb] = MT::mfma(va, fi, ti[cb]);
-                ti[cb] = MT::mfma(vai, fr, ti[cb]);
+                fr[cb] = __builtin_bit_cast(vec, *reinterpret_cast<const u32x4*>(a.Fr + o));
+                fi[cb] = __builtin_bit_cast(vec, *reinterpret_cast<const u32x4*>(a.Fi + o));
+            }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                // A fragments: lag products of this lane's row at 8 consecutive samples
+                const int row = wrow * 64 + rb * 32 + (lane & 31);
+                u32x4 par, pai;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned int wr = 0, wi = 0;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int t = ks * 16 + kg * 8 + 2 * q + h;
+                        const float2 x = s_yi[t];
+                        const float2 y = s_yj[t + row];
+                        const float lr = fmaf(x.x, y.x, x.y * y.y);  // x * conj(y)
+                        const float li = fmaf(x.y, y.x, -(x.x * y.y));
+                        wr |= (unsigned int)MT::cvt(lr) << (16 * h);
+                        wi |= (unsigned int)MT::cvt(li) << (16 * h);
+                    }
+                    par[q] = wr;
+                    pai[q] = wi;
+                }
+                const u32x4 pnai = pai ^ 0x80008000u;   // -Ai: flip both sign bits of each word
+                const vec va = __builtin_bit_cast(vec, par);
+                const vec vai = __builtin_bit_cast(vec, pai);
+                const vec vnai = __builtin_bit_cast(vec, pnai);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    tr[rb][cb] = MT::mfma(va, fr[cb], tr[rb][cb]);
+                    tr[rb][cb] = MT::mfma(vnai, fi[cb], tr[rb][cb]);
+                    ti[rb][cb] = MT::mfma(va, fi[cb], ti[rb][cb]);
+                    ti[rb][cb] = MT::mfma(vai, fr[cb], ti[rb][cb]);
+                }
             }
         }
     }
 
-    // epilogue: rows 8 (i/4) + 4 (lane/32) + i%4 of this wave's 32-row block, column lane % 32
+    // epilogue: rows 8 (i/4) + 4 (lane/32) + i%4 of each 32-row block, column lane % 32
     float2* out = a.out + ((int64_t)split * a.n_pairs * a.kc + ek) * (int64_t)a.n_lags_pad * a.M_pad;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = lag_base + wrow * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-            const int c = bin_base + cb * 32 + (lane & 31);
-            out[(int64_t)r * a.M_pad + c] = make_float2(tr[cb][i] * a.unscale, ti[cb][i] * a.unscale);
-        }
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = lag_base + wrow * 64 + rb * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+                const int c = bin_base + cb * 32 + (lane & 31);
+                out[(int64_t)r * a.M_pad + c] = make_float2(tr[rb][cb][i] * a.unscale, ti[rb][cb][i] * a.unscale);
+            }
 }
 
 __global__ __launch_bounds__(256) void k_caf_reduce(const float2* __restrict__ part, int64_t n, int32_t n_split,
@@ -344,7 +364,8 @@ hipError_t launch_caf_phasor(bool f16, int32_t L_pad, int32_t L, int32_t M, int3
 }
 
 hipError_t launch_caf_gemm(bool f16, const CafGemmArgs& a, hipStream_t s) {
-    dim3 grid((unsigned)(a.n_lags_pad / 64), (unsigned)(a.M_pad / 256), (unsigned)(a.n_split * a.n_pairs * a.kc));
+    dim3 grid((unsigned)(a.n_lags_pad / kCafTileLags), (unsigned)(a.M_pad / kCafTileBins),
+              (unsigned)(a.n_split * a.n_pairs * a.kc));
     if (f16)
         hipLaunchKernelGGL(k_caf_gemm<true>, grid, dim3(256), 0, s, a);
     else
