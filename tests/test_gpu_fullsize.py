@@ -1,0 +1,123 @@
+"""Parity at the full sizes of the proposal and continental workloads, in the launch
+configurations a user of those workloads gets: sampled points against the FP64 oracle,
+the peaks, and (continental) the BF16 CAF-table map's two peaks against the direct map's."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import DIRECT_TOL, err_J, log, require_gpu
+from paper_2508_06672_amd import configs, sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2508_06672_amd import geoloc
+    geoloc.load()
+    return geoloc
+
+
+def _window(idx: int, n_rows: int, n_cols: int, r: int):
+    r0, c0 = divmod(int(idx), n_cols)
+    return [rr * n_cols + cc for rr in range(max(0, r0 - r), min(n_rows, r0 + r + 1))
+            for cc in range(max(0, c0 - r), min(n_cols, c0 + r + 1))]
+
+
+def _sampled_parity(scn_lat, scn_lon, wl, Jg, caps_np, states, pairs, step_len, fs, peaks, seed, n_random=256, r=5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = [rng.choice(wl.n_points, n_random, replace=False)]
+    for a in peaks:
+        idx.append(np.array(_window(a, wl.n_rows, wl.n_cols, r)))
+    idx = np.unique(np.concatenate(idx))
+    rows, cols = np.divmod(idx, wl.n_cols)
+    log(f"  oracle at {idx.size} points")
+    Jo = oracle.map_points(scn_lat[rows], scn_lon[cols], caps_np, states, step_len, fs, wl.fc_hz,
+                           pairs=pairs, radius=wl.earth_radius_m)
+    e = float(np.max(np.abs(Jg[idx] - Jo)) / np.max(Jo))
+    return idx, Jo, e
+
+
+def test_proposal_workload_separate_captures(torch, G):
+    """1024 x 1024 grid, 10 captures of 100,000 samples (one coherent step each) stacked as
+    20 virtual receivers with 10 pairs: the direct map at 256 random cells and around its
+    peak matches the oracle, and the peak is the oracle's best sampled cell."""
+    from paper_2508_06672_amd import proposal as P
+    wl = configs.PROPOSAL
+    snaps = sim.make_snapshots(wl, 1_030_005)
+    capn, states, vpairs = P.stack_snapshots(snaps, wl.pairs)
+    s0 = snaps[0]
+    caps = torch.from_numpy(capn).cuda()
+    with G.Plan(n_rx=capn.shape[0], n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                lat=s0.lat, lon=s0.lon, pairs=vpairs, earth_radius_m=wl.earth_radius_m) as plan:
+        J = plan.map(caps, states)
+        idx, val = plan.argmax(J)
+        info = plan.info()
+        Jg = J.cpu().numpy().astype(np.float64)
+    log(f"proposal full size: tile {info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear']}, "
+        f"peak {int(idx[0])}")
+    sidx, Jo, e = _sampled_parity(s0.lat, s0.lon, wl, Jg, capn, states, vpairs, wl.step_len, wl.fs_hz,
+                                  [int(idx[0])], 31)
+    log(f"  err_J = {e:.3g}")
+    assert e <= DIRECT_TOL
+    assert Jo[np.searchsorted(sidx, int(idx[0]))] >= (1 - 2 * DIRECT_TOL) * np.max(Jo)
+
+
+def test_continental_direct_and_caf(torch, G):
+    """4000 x 4000 grid at 0.5 km (1.6e7 points), 3 receivers and 3 pairs, 4e6 samples at
+    20 MHz in 200 steps, two emitters at -20 dB. The direct map matches the oracle at
+    sampled cells and around both of its peaks; the BF16 CAF-table map finds the same two
+    peaks (within one cell, on the orbital-plane mirror, or tol-optimal on the direct map)."""
+    wl = configs.CONTINENTAL
+    t0 = time.time()
+    scn = sim.make_scenario(wl, 0)
+    log(f"continental: simulated in {time.time() - t0:.0f} s")
+    caps = torch.from_numpy(scn.captures).cuda()
+    nms = 8
+    with G.Plan.for_scenario(scn) as plan:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        J = plan.map(caps, scn.states)
+        torch.cuda.synchronize()
+        t_map = time.time() - t0
+        pk, pv = plan.argmax(J, top_k=2, nms_radius=nms)
+        info = plan.info()
+        Jg = J.cpu().numpy().astype(np.float64)
+    log(f"  direct map {t_map:.2f} s ({wl.units / t_map:.3g} correlations/s), tile {info['tile_rows']}x"
+        f"{info['tile_cols']} shear {info['tile_shear']} transpose {info['tile_transpose']}, peaks {list(pk)}")
+    sidx, Jo, e = _sampled_parity(scn.lat, scn.lon, wl, Jg, scn.captures, scn.states, list(wl.pairs), wl.step_len,
+                                  wl.fs_hz, [int(p) for p in pk], 32, n_random=192, r=3)
+    log(f"  err_J = {e:.3g}")
+    assert e <= DIRECT_TOL
+    for p in pk:
+        near = np.array(_window(p, wl.n_rows, wl.n_cols, 3))
+        sel = np.searchsorted(sidx, near)
+        assert Jo[np.searchsorted(sidx, int(p))] >= (1 - 2 * DIRECT_TOL) * np.max(Jo[sel])
+
+    with G.Plan.for_scenario(scn, method=G.CAF_BF16) as cplan:
+        t0 = time.time()
+        Jc = cplan.map(caps, scn.states)
+        torch.cuda.synchronize()
+        t_caf = time.time() - t0
+        ck, _ = cplan.argmax(Jc, top_k=2, nms_radius=nms)
+        Jc = Jc.cpu().numpy().astype(np.float64)
+    ec = err_J(Jc, Jg)
+    log(f"  CAF BF16 map {t_caf:.2f} s, err vs direct {ec:.3g}, peaks {list(ck)}")
+    assert ec <= 1e-2
+
+    def agrees(a: int) -> bool:
+        r, c = divmod(a, wl.n_cols)
+        for p in pk:
+            pr, pc = divmod(int(p), wl.n_cols)
+            mr, mc = sim.nearest_cell(scn.lat, scn.lon, *sim.mirror_latlon(wl, scn.lat[pr], scn.lon[pc]))
+            if max(abs(r - pr), abs(c - pc)) <= 1 or max(abs(r - mr), abs(c - mc)) <= 1:
+                return True
+        return Jg[a] >= (1 - 2e-2) * Jg[int(pk[1])]
+    assert all(agrees(int(a)) for a in ck), (list(ck), list(pk))
