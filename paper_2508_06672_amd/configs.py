@@ -115,4 +115,18 @@ CONTINENTAL = Workload(
     n_emitters=2, pairs=((0, 1), (0, 2), (1, 2)),
 )
 
-ALL = {w.name: w for w in (SMALL, MAP_1E6, CAF_SMALL, PROPOSAL, CONTINENTAL)}
+# The multi-capture scenario of Sec. IV-B: 58 captures of 50 ms at 5 MHz, 1 s apart, each
+# correlated coherently as one step and accumulated; four emitters in a rectangle (a
+# spread-spectrum stand-in for the L1 C/A spoofer, a tone at the carrier, a 2 MHz / 20 us
+# chirp and a 200 kHz / 5 ms sawtooth, equal power; see sim.paper_formation). The receivers
+# fly 50 km apart along track with a 30 km cross-track offset (two neighbouring orbital
+# planes), which removes the exact mirror twin of every peak; 1000 x 450 cells at 1 km.
+PAPER_IVB = Workload(
+    name="paper_58x50ms_5MHz",
+    rx_along_track_m=(-25.0e3, 25.0e3), rx_cross_track_m=(0.0, 30.0e3),
+    n_rows=450, n_cols=1000, spacing_m=1000.0,
+    fs_hz=5.0e6, n_samples=250_000, step_len=250_000, n_snapshots=58, snapshot_spacing_s=1.0,
+    waveform="tone", snr_db=-10.0, n_emitters=4,
+)
+
+ALL = {w.name: w for w in (SMALL, MAP_1E6, CAF_SMALL, PROPOSAL, CONTINENTAL, PAPER_IVB)}

@@ -48,6 +48,9 @@ class Emitter:
     waveform: str
     tone_hz: float = 0.0
     power: float = 1.0
+    bw_hz: float = 0.0          # chirp / sawtooth sweep (0: the workload's)
+    period_s: float = 0.0       # chirp / sawtooth period (0: the workload's)
+    code_seed: int = 0          # bpsk: seed of its spreading and data bits
 
 
 @dataclass
@@ -166,6 +169,21 @@ def tone(t: np.ndarray, f0: float) -> np.ndarray:
     return np.exp(2j * np.pi * np.mod(f0 * t, 1.0))
 
 
+def bpsk(t: np.ndarray, seed: int, chip_rate: float = 1.023e6, n_chips: int = 1023, bit_rate: float = 50.0,
+         n_bits: int = 1500) -> np.ndarray:
+    """Spread-spectrum stand-in for a GPS L1 C/A-like signal (Sec. IV-A): a seeded random
+    +-1 code of n_chips chips at chip_rate, repeating every n_chips / chip_rate seconds,
+    times seeded random +-1 data bits at bit_rate (n_bits of them, then repeating). The
+    published C/A Gold codes are not used."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    code = rng.choice(np.array([-1.0, 1.0]), n_chips)
+    data = rng.choice(np.array([-1.0, 1.0]), n_bits)
+    t = np.asarray(t, dtype=np.float64)
+    ci = np.mod(np.floor(t * chip_rate).astype(np.int64), n_chips)
+    bi = np.mod(np.floor(t * bit_rate).astype(np.int64), n_bits)
+    return (code[ci] * data[bi]).astype(np.complex128)
+
+
 class BandlimitedGaussian:
     """Complex Gaussian noise of unit power, band-limited to |f| < bw/2, defined on
     continuous time through a 32-tap Kaiser-windowed sinc interpolator."""
@@ -215,11 +233,12 @@ def _pick_waveform(wl: Workload, rng: np.random.Generator) -> str:
 
 def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noiseless: bool = False,
                   emitter_latlon: Optional[List[Tuple[float, float]]] = None,
-                  waveform: Optional[str] = None, t_offset_s: float = 0.0, stream: int = 0) -> Scenario:
+                  waveform: Optional[str] = None, t_offset_s: float = 0.0, stream: int = 0,
+                  emitters: Optional[List[Emitter]] = None) -> Scenario:
     """One capture of n_samples centred t_offset_s after the reference instant of the
     seed's geometry. Geometry, emitter and SNR come from the seed alone; `stream` > 0
     draws the waveform and the receiver noise from a stream of their own (the separate
-    snapshots of one scenario)."""
+    snapshots of one scenario). `emitters` replaces the drawn emitters by given ones."""
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(3 + max(3, wl.n_rx))
     rng_geo, rng_em, rng_wave = (np.random.Generator(np.random.PCG64(k)) for k in kids[:3])
@@ -237,7 +256,7 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
     if snr_db is None:
         snr_db = float(rng_em.uniform(*wl.snr_db_range)) if wl.snr_db_range else wl.snr_db
 
-    emitters: List[Emitter] = []
+    drawn: List[Emitter] = []
     for e in range(wl.n_emitters):
         if emitter_latlon is not None:
             la, lo = emitter_latlon[e]
@@ -247,7 +266,11 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
         wf = waveform or _pick_waveform(wl, rng_em)
         f0 = float(rng_em.uniform(-wl.tone_offset_max_hz, wl.tone_offset_max_hz)) if wl.tone_offset_max_hz else 0.0
         power = 2.0 if wf == "chirp+gauss" else 1.0
-        emitters.append(Emitter(la, lo, wf, f0, power))
+        drawn.append(Emitter(la, lo, wf, f0, power))
+    if emitters is not None:
+        emitters = list(emitters)
+    else:
+        emitters = drawn
 
     N, fs = wl.n_samples, wl.fs_hz
     t_abs = t_offset_s + np.arange(N, dtype=np.float64) / fs
@@ -266,12 +289,16 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
                                         wl.gauss_bw_hz)
         for i in range(wl.n_rx):
             te = t_abs - taus[i]                                  # emission time of what arrives at t_n
+            bw = em.bw_hz or wl.chirp_bw_hz
+            period = em.period_s or wl.chirp_period_s
             if em.waveform == "tone":
                 x = tone(te, em.tone_hz)
             elif em.waveform == "chirp":
-                x = chirp(te, wl.chirp_bw_hz, wl.chirp_period_s)
+                x = chirp(te, bw, period)
             elif em.waveform == "sawtooth":
-                x = sawtooth(te, wl.chirp_bw_hz, wl.chirp_period_s)
+                x = sawtooth(te, bw, period)
+            elif em.waveform == "bpsk":
+                x = bpsk(te, em.code_seed)
             elif em.waveform == "gauss":
                 x = gauss(te)
             elif em.waveform == "chirp+gauss":
@@ -294,6 +321,32 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
     mirror_cells = [nearest_cell(lat, lon, *mirror_latlon(wl, em.lat, em.lon)) for em in emitters]
     return Scenario(wl, seed, lat, lon, states, np.ascontiguousarray(y.astype(np.complex64)),
                     emitters, true_cells, mirror_cells, noise_var, snr_db, u_mid)
+
+
+def reference_grid(wl: Workload, seed: int):
+    """(lat, lon, u_mid) of a seed's scenario without simulating it (the geometry stream's
+    first draw, as in make_scenario)."""
+    kids = np.random.SeedSequence(seed).spawn(3 + max(3, wl.n_rx))
+    u_mid = float(np.random.Generator(np.random.PCG64(kids[0])).uniform(0.0, 2.0 * math.pi))
+    lat, lon = make_grid(wl, u_mid)
+    return lat, lon, u_mid
+
+
+def paper_formation(wl: Workload, seed: int, d_rows: float = 100.4, d_cols: float = 250.3) -> List[Emitter]:
+    """Four emitters at the corners of a rectangle centred on the grid (Sec. IV-B): a
+    spread-spectrum stand-in for the L1 C/A spoofer, a tone at the carrier, a chirp of
+    2 MHz and 20 us, and a sawtooth of 200 kHz and 5 ms, at equal power. Offsets in cells,
+    deliberately off the grid nodes."""
+    lat, lon, _ = reference_grid(wl, seed)
+    dlat, dlon = lat[1] - lat[0], lon[1] - lon[0]
+    r0, c0 = (lat.size - 1) / 2.0, (lon.size - 1) / 2.0
+    spec = [("bpsk", -1, -1, 0.0, 0.0), ("tone", -1, 1, 0.0, 0.0), ("chirp", 1, -1, 2.0e6, 20e-6),
+            ("sawtooth", 1, 1, 200e3, 5e-3)]
+    out = []
+    for i, (wf, sr, sc, bw, per) in enumerate(spec):
+        out.append(Emitter(lat[0] + dlat * (r0 + sr * d_rows), lon[0] + dlon * (c0 + sc * d_cols), wf, 0.0, 1.0,
+                           bw, per, code_seed=seed * 16 + i))
+    return out
 
 
 def snapshot_offsets(wl: Workload) -> np.ndarray:
