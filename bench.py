@@ -246,6 +246,40 @@ def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
             "within_one_cell_or_tol_optimal": optimal / n}
 
 
+def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
+    """One training step of the proposal CNN (forward, softmax cross-entropy, backward,
+    Adam) on a batch of 64 coarse-map feature stacks, through the library's kernels."""
+    import numpy as np
+    import torch
+    from paper_2508_06672_amd import proposal as P
+    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=batch)
+    try:
+        net.set_params(theta)
+        g = torch.Generator(device="cuda").manual_seed(0)
+        x = torch.randn((batch, P.IN_CH, P.COARSE, P.COARSE), device="cuda", generator=g)
+        y = torch.zeros((batch, P.COARSE * P.COARSE), device="cuda")
+        y[torch.arange(batch), torch.randint(0, P.COARSE * P.COARSE, (batch,), device="cuda", generator=g)] = 1.0
+
+        def step():
+            z = net.forward(x)
+            _, dz = net.loss(z, y)
+            net.backward(dz)
+            net.adam_step(1e-4)
+
+        step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+    finally:
+        net.close()
+    return {"batch": batch, "ms": ms, "samples_per_s": batch / (ms / 1e3), "params": int(theta.size)}
+
+
 def learned_leg(geoloc, seeds):
     """The learned tile proposal with its stored weights and calibrated fallback on held-out
     proposal scenarios: median time against the full plain map of the same scenario, and
@@ -263,7 +297,8 @@ def learned_leg(geoloc, seeds):
         prop.close()
         net.close()
     L, A = res["learned"], res["coarse_top16_ablation"]
-    return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"],
+    train = train_step_leg(geoloc, theta)
+    return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"], "train_step": train,
             "threshold": meta["threshold"], "full_map_median_ms": res["full_map_median_ms"],
             "median_ms": L["median_ms"], "speedup_vs_full_median": L["speedup_vs_full_median"],
             "agree_rate": L["agree_rate"], "fallback_rate": L["fallback_rate"],

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <new>
 #include <string>
 #include <vector>
@@ -246,59 +247,65 @@ void host_delay_doppler(const geoloc_plan_s* p, double lat, double lon, const do
 }
 
 // Tile shape for the factored kernel: from the delay and Doppler gradients at the grid
-// centre (first pair, middle step), the candidate with the least predicted VALU work per
-// correlation, counting the lanes its tiles leave outside the grid. The lag moments cost
-// about (8 + 4Q) / NB instructions per correlation (NB blocks per round, from the lag
-// spread H) and the per-point combination (6Q + 8) / 64; a tile that the factored kernel
-// would defer costs about 13.
+// centre (middle step) of every pair, the candidate with the least predicted VALU work per
+// correlation summed over the pairs, counting the lanes its tiles leave outside the grid.
+// The lag moments cost about (8 + 4Q) / NB instructions per correlation (NB blocks per
+// round, from the lag spread H) and the per-point combination (6Q + 8) / 64; a tile that
+// the factored kernel would defer costs about 13.
 void choose_tiling(geoloc_plan_t p, const double* states) {
     p->tiling = p->base_tiling;
     if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 || p->tile_shapes.empty()) return;
     const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
-    const int2 pr = p->pairs[0];
-    const double* si = states + ((size_t)k * p->n_rx + pr.x) * 6;
-    const double* sj = states + ((size_t)k * p->n_rx + pr.y) * 6;
-    auto dd = [&](int64_t r, int64_t c, double* D, double* th) {
-        host_delay_doppler(p, p->h_lat[r], p->h_lon[c], si, sj, D, th);
-    };
-    double g[2][2] = {{0, 0}, {0, 0}};   // [delay, doppler][d/drow, d/dcol]
     const int64_t ra = std::max<int64_t>(r0 - 1, 0), rb = std::min<int64_t>(r0 + 1, p->rows - 1);
     const int64_t ca = std::max<int64_t>(c0 - 1, 0), cb = std::min<int64_t>(c0 + 1, p->cols - 1);
-    double D1, t1, D2, t2;
-    if (rb > ra) {
-        dd(ra, c0, &D1, &t1);
-        dd(rb, c0, &D2, &t2);
-        g[0][0] = (D2 - D1) / (double)(rb - ra);
-        g[1][0] = (t2 - t1) / (double)(rb - ra);
+    // gradients [pair][delay, doppler][d/drow, d/dcol]
+    std::vector<std::array<double, 4>> grads;
+    for (const int2 pr : p->pairs) {
+        const double* si = states + ((size_t)k * p->n_rx + pr.x) * 6;
+        const double* sj = states + ((size_t)k * p->n_rx + pr.y) * 6;
+        std::array<double, 4> g{0, 0, 0, 0};
+        double D1, t1, D2, t2;
+        if (rb > ra) {
+            host_delay_doppler(p, p->h_lat[ra], p->h_lon[c0], si, sj, &D1, &t1);
+            host_delay_doppler(p, p->h_lat[rb], p->h_lon[c0], si, sj, &D2, &t2);
+            g[0] = (D2 - D1) / (double)(rb - ra);
+            g[2] = (t2 - t1) / (double)(rb - ra);
+        }
+        if (cb > ca) {
+            host_delay_doppler(p, p->h_lat[r0], p->h_lon[ca], si, sj, &D1, &t1);
+            host_delay_doppler(p, p->h_lat[r0], p->h_lon[cb], si, sj, &D2, &t2);
+            g[1] = (D2 - D1) / (double)(cb - ca);
+            g[3] = (t2 - t1) / (double)(cb - ca);
+        }
+        if (!std::isfinite(g[0] + g[1] + g[2] + g[3])) return;
+        grads.push_back(g);
     }
-    if (cb > ca) {
-        dd(r0, ca, &D1, &t1);
-        dd(r0, cb, &D2, &t2);
-        g[0][1] = (D2 - D1) / (double)(cb - ca);
-        g[1][1] = (t2 - t1) / (double)(cb - ca);
-    }
-    if (!std::isfinite(g[0][0] + g[0][1] + g[1][0] + g[1][1])) return;
     auto cost = [&](const PointTiling& t) {
-        const double gr = t.transpose ? g[0][1] : g[0][0], gc = t.transpose ? g[0][0] : g[0][1];
-        const double hr = t.transpose ? g[1][1] : g[1][0], hc = t.transpose ? g[1][0] : g[1][1];
-        const double H = std::fabs(gr + t.shear * gc) * (t.tile_h - 1) + std::fabs(gc) * (t.tile_w - 1) + 3.0;
-        const double xr = 0.5 * (std::fabs(hr + t.shear * hc) * (t.tile_h - 1) + std::fabs(hc) * (t.tile_w - 1)) * 32.0;
-        int Q = 0;
-        double term = 1.0;
-        for (int q = 1; q <= 4 && xr < 1.0; ++q) {
-            term *= xr / q;
-            if (term <= 5.9604645e-8) {
-                Q = q;
-                break;
+        double total = 0.0;
+        for (const auto& g : grads) {
+            const double gr = t.transpose ? g[1] : g[0], gc = t.transpose ? g[0] : g[1];
+            const double hr = t.transpose ? g[3] : g[2], hc = t.transpose ? g[2] : g[3];
+            const double H = std::fabs(gr + t.shear * gc) * (t.tile_h - 1) + std::fabs(gc) * (t.tile_w - 1) + 3.0;
+            const double xr =
+                0.5 * (std::fabs(hr + t.shear * hc) * (t.tile_h - 1) + std::fabs(hc) * (t.tile_w - 1)) * 32.0;
+            int Q = 0;
+            double term = 1.0;
+            for (int q = 1; q <= 4 && xr < 1.0; ++q) {
+                term *= xr / q;
+                if (term <= 5.9604645e-8) {
+                    Q = q;
+                    break;
+                }
             }
+            double c = 13.0;
+            if (Q > 0 && H <= 128.0) {
+                const int Hg = (int)std::ceil(H / 2.0);
+                const int NB = std::min(32, 256 / Hg);
+                c = (8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0;
+            }
+            total += c;
         }
-        double c = 13.0;
-        if (Q > 0 && H <= 128.0) {
-            const int Hg = (int)std::ceil(H / 2.0);
-            const int NB = std::min(32, 256 / Hg);
-            c = (8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0;
-        }
-        return c * (double)(t.tiles_x * t.tiles_y * kTilePoints) / (double)p->P;
+        return total * (double)(t.tiles_x * t.tiles_y * kTilePoints) / (double)p->P;
     };
     double best = cost(p->base_tiling);
     for (const auto& t : p->tile_shapes) {
