@@ -7,7 +7,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Contents
   * ``geoloc_oracle.c`` (built to ``liboracle.so`` with gcc, -O2 -fopenmp
     -ffp-contract=off): grid -> ECEF, geometry (Eq. (3)-(9)), one correlation
-    (Eq. (11)), the full map (Algorithm 1, accumulated over steps and pairs).
+    (Eq. (11)) with a ROUND, LINEAR or eight-tap windowed-sinc delay, the full map
+    (Algorithm 1, accumulated over steps and pairs).
   * ``caf.py``: the FP64 CAF-table form of Eq. (11) (lag-product matrix times a
     Doppler phasor matrix, then bilinear interpolation in lag and Doppler).
   * ``brute.py``: Eq. (11) written as literal Python loops, for tiny inputs.
@@ -25,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-LINEAR, ROUND = 0, 1
+LINEAR, ROUND, SINC = 0, 1, 2
 POWER, MAG = 0, 1
 
 _lib = None
@@ -46,6 +47,7 @@ def _load():
         lib.oracle_geometry.argtypes = [i64, dp, i32, i32, dp, i32, i32, f64, f64, dp, dp]
         lib.oracle_corr.argtypes = [fp, fp, i64, i64, i64, f64, f64, f64, i32, dp, dp]
         lib.oracle_map.argtypes = [i64, dp, dp, f64, f64, i32, i64, i64, fp, dp, i32, ip, f64, f64, i32, i32, dp]
+        lib.oracle_sinc_taps.argtypes = [f64, dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -92,6 +94,13 @@ def set_threads(n: int) -> None:
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def sinc_taps(alpha: float) -> np.ndarray:
+    """The eight SINC-mode weights for fractional delay alpha (taps -3 .. 4 around floor(D))."""
+    w = np.empty(8)
+    _load().oracle_sinc_taps(float(alpha), _dptr(w))
+    return w
 
 
 def grid_ecef(lat, lon, radius: float = 6371.0e3, alt: float = 0.0) -> np.ndarray:

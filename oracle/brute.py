@@ -26,6 +26,14 @@ def _tau_f(q, s, lam):
     return rho / C, f
 
 
+def _sinc_weights(a: float):
+    """Eight weights of the windowed-sinc delay (taps -3 .. 4), from numpy's sinc and I0."""
+    x = np.arange(-3, 5) - a
+    g = np.where(np.abs(x) < 4.0, np.sinc(x) * np.i0(6.0 * np.sqrt(np.clip(1.0 - (x / 4.0) ** 2, 0.0, None)))
+                 / np.i0(6.0), 0.0)
+    return [float(v) for v in g / g.sum()]
+
+
 def brute_map(lat_p: Sequence[float], lon_p: Sequence[float], captures: np.ndarray, states: np.ndarray,
               step_len: int, fs: float, fc: float, pairs: Sequence[Tuple[int, int]], radius: float = 6371.0e3,
               delay_mode: int = 0, accum_mode: int = 0) -> np.ndarray:
@@ -52,9 +60,13 @@ def brute_map(lat_p: Sequence[float], lon_p: Sequence[float], captures: np.ndarr
                 else:
                     d0 = math.floor(D)
                     a = D - d0
+                w = _sinc_weights(a) if delay_mode == 2 else None
                 s = 0j
                 for n in range(k * step_len, (k + 1) * step_len):
-                    yt = (1 - a) * sample(j, n + d0) + a * sample(j, n + d0 + 1)
+                    if w is None:
+                        yt = (1 - a) * sample(j, n + d0) + a * sample(j, n + d0 + 1)
+                    else:
+                        yt = sum(w[t + 3] * sample(j, n + d0 + t) for t in range(-3, 5))
                     t = (n - k * step_len - (step_len - 1) / 2) / fs
                     s += sample(i, n) * yt.conjugate() * cmath.exp(2j * math.pi * nu * t)
                 J[p] += abs(s) if accum_mode == 1 else abs(s) ** 2

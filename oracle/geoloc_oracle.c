@@ -11,8 +11,9 @@
  *   geometry ................ Sec. II-B, Eq. (3)-(8): range vector, range / delay, unit range
  *                             vector, Doppler f = -(1/lambda) r_hat . v, TDOA, FDOA.
  *   delay in samples ........ Eq. (9) with the dimensional reading D = dTau * f_s; the
- *                             paper's integer rounding (ROUND mode) and a two-tap linear
- *                             fractional delay (LINEAR mode, default).
+ *                             paper's integer rounding (ROUND mode), a two-tap linear
+ *                             fractional delay (LINEAR mode, default) and an eight-tap
+ *                             Kaiser-windowed sinc fractional delay (SINC mode).
  *   correlation ............. Eq. (10)-(11) per snapshot (step) k, with the sample time t_n
  *                             measured from the step centre and y_j = 0 outside the capture.
  *   map ..................... Algorithm 1 "sum the grids": J(p) = sum over pairs and steps of
@@ -31,7 +32,9 @@
 #define ORC_C_LIGHT 299792458.0
 #define ORC_PI 3.14159265358979323846
 
-enum { ORC_LINEAR = 0, ORC_ROUND = 1 };
+enum { ORC_LINEAR = 0, ORC_ROUND = 1, ORC_SINC = 2 };
+#define ORC_SINC_HALF 4        /* taps t = -3 .. 4 around floor(D) */
+#define ORC_SINC_BETA 6.0      /* Kaiser window shape */
 enum { ORC_POWER = 0, ORC_MAG = 1 };
 
 int oracle_abi_version(void) { return 1; }
@@ -113,6 +116,38 @@ static void split_delay(double D, int mode, int64_t* d0, double* alpha) {
     }
 }
 
+/* Modified Bessel function of the first kind, order 0: sum_k ((x/2)^k / k!)^2. */
+static double bessel_i0(double x) {
+    double q = 0.25 * x * x, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+/* Kaiser-windowed sinc g(x) = sinc(x) I0(beta sqrt(1 - (x/4)^2)) / I0(beta) for |x| < 4,
+ * 0 outside; sinc(x) = sin(pi x) / (pi x). */
+static double windowed_sinc(double x) {
+    const double h = (double)ORC_SINC_HALF;
+    if (fabs(x) >= h) return 0.0;
+    const double s = x == 0.0 ? 1.0 : sin(ORC_PI * x) / (ORC_PI * x);
+    const double u = x / h;
+    return s * bessel_i0(ORC_SINC_BETA * sqrt(1.0 - u * u)) / bessel_i0(ORC_SINC_BETA);
+}
+
+/* The eight weights of a delay with fractional part alpha: w[t + 3] = g(t - alpha) /
+ * sum_s g(s - alpha), t = -3 .. 4 (unit gain at zero frequency). */
+void oracle_sinc_taps(double alpha, double* w) {
+    double sum = 0.0;
+    for (int t = -ORC_SINC_HALF + 1; t <= ORC_SINC_HALF; ++t) {
+        w[t + ORC_SINC_HALF - 1] = windowed_sinc((double)t - alpha);
+        sum += w[t + ORC_SINC_HALF - 1];
+    }
+    for (int i = 0; i < 2 * ORC_SINC_HALF; ++i) w[i] /= sum;
+}
+
 /* One correlation C_k for delay D (samples) and FDOA nu (Hz), Eq. (11) over step k:
  *   C = sum_{n=kL}^{kL+L-1} y_i[n] * conj(ytilde_j[n]) * exp(+j 2 pi nu t_n),
  *   t_n = (n - kL - (L-1)/2) / f_s,
@@ -122,6 +157,8 @@ void oracle_corr(const float* yi, const float* yj, int64_t n_samples, int64_t k,
     int64_t d0;
     double alpha;
     split_delay(D, delay_mode, &d0, &alpha);
+    double w[2 * ORC_SINC_HALF];
+    if (delay_mode == ORC_SINC) oracle_sinc_taps(alpha, w);
     double sr = 0.0, si = 0.0;
     for (int64_t n = k * step_len; n < (k + 1) * step_len; ++n) {
         double ar, ai, br, bi, xr, xi;
@@ -129,6 +166,17 @@ void oracle_corr(const float* yi, const float* yj, int64_t n_samples, int64_t k,
         sample_at(yj, n_samples, n + d0 + 1, &br, &bi);
         double ytr = (1.0 - alpha) * ar + alpha * br;
         double yti = (1.0 - alpha) * ai + alpha * bi;
+        if (delay_mode == ORC_SINC) {
+            /* ytilde_j[n] = sum_{t=-3}^{4} w[t] y_j[n + d0 + t] */
+            ytr = 0.0;
+            yti = 0.0;
+            for (int t = -ORC_SINC_HALF + 1; t <= ORC_SINC_HALF; ++t) {
+                double cr, ci;
+                sample_at(yj, n_samples, n + d0 + t, &cr, &ci);
+                ytr += w[t + ORC_SINC_HALF - 1] * cr;
+                yti += w[t + ORC_SINC_HALF - 1] * ci;
+            }
+        }
         sample_at(yi, n_samples, n, &xr, &xi);
         /* x * conj(ytilde) */
         double pr = xr * ytr + xi * yti;

@@ -1,6 +1,7 @@
 """Plant plausible mistakes in the oracle's C source (on the CPU) and check that the pins
 catch every one: a wrong sign, a swapped weight, a missing conjugate, an index off by one,
-broken zero padding, a swapped accumulation mode or a wrong coordinate."""
+broken zero padding, a swapped accumulation mode, a wrong coordinate, unnormalised or
+shifted windowed-sinc taps."""
 import os
 import subprocess
 
@@ -25,6 +26,10 @@ MUTANTS = {
     "round_is_floor": ("*d0 = (int64_t)round(D);", "*d0 = (int64_t)floor(D);"),
     "step_sum_range": ("for (int64_t n = k * step_len; n < (k + 1) * step_len; ++n) {",
                        "for (int64_t n = k * step_len; n + 1 < (k + 1) * step_len; ++n) {"),
+    "sinc_taps_unnormalised": ("for (int i = 0; i < 2 * ORC_SINC_HALF; ++i) w[i] /= sum;",
+                               "for (int i = 0; i < 2 * ORC_SINC_HALF; ++i) w[i] /= 1.0;"),
+    "sinc_tap_offset": ("sample_at(yj, n_samples, n + d0 + t, &cr, &ci);",
+                        "sample_at(yj, n_samples, n + d0 + t + 1, &cr, &ci);"),
 }
 
 PINS = [getattr(pins, n) for n in dir(pins) if n.startswith("test_") and n != "test_peaks_rules"]
