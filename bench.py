@@ -305,6 +305,27 @@ def learned_leg(geoloc, seeds):
             "ablation_agree_rate": A["agree_rate"], "ablation_speedup_vs_full_median": A["speedup_vs_full_median"]}
 
 
+def delay_modes_leg(geoloc, torch, scn, caps):
+    """The benchmark map in each delay mode: time per map (after one warm-up), the peak
+    value and cell. The peak ratio to SINC shows what the two-tap and integer delays lose
+    to scalloping on this emitter."""
+    out = {}
+    for name, mode in (("linear", geoloc.DELAY_LINEAR), ("round", geoloc.DELAY_ROUND), ("sinc", geoloc.DELAY_SINC)):
+        with geoloc.Plan.for_scenario(scn, delay_mode=mode) as plan:
+            J = plan.map(caps, scn.states)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.map(caps, scn.states, J=J)
+            e1.record()
+            torch.cuda.synchronize()
+            idx, val = plan.argmax(J)
+        out[name] = {"map_ms": e0.elapsed_time(e1), "peak": float(val[0]), "argmax": int(idx[0])}
+    for name in ("linear", "round"):
+        out[name]["peak_vs_sinc"] = out[name]["peak"] / out["sinc"]["peak"]
+    return out
+
+
 def paper_leg(geoloc, torch, seed: int = 7, reps: int = 3):
     """The multi-capture scenario of Sec. IV-B (58 captures of 50 ms at 5 MHz, 1 s apart,
     four emitters): time of the accumulated map over 116 virtual receivers, and how many
@@ -349,6 +370,7 @@ def main() -> int:
     ap.add_argument("--proposal-seeds", type=int, default=8,
                     help="held-out scenarios for the learned-proposal leg (0 skips it)")
     ap.add_argument("--no-paper-scenario", action="store_true", help="skip the 58-capture scenario leg")
+    ap.add_argument("--no-delay-modes", action="store_true", help="skip the ROUND / SINC delay-mode leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -439,6 +461,11 @@ def main() -> int:
             log(f"caf agreement over {args.agreement_seeds} seeds")
             caf["agreement_bf16"] = agreement(geoloc, torch, wl, list(range(10000, 10000 + args.agreement_seeds)))
 
+    modes = None
+    if not args.no_delay_modes:
+        log("delay modes")
+        modes = delay_modes_leg(geoloc, torch, scn, caps)
+
     learned = None
     if args.proposal_seeds > 0:
         from paper_2508_06672_amd import proposal as P
@@ -470,6 +497,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "caf": caf,
+        "delay_modes": modes,
         "learned": learned,
         "paper_scenario": paper,
     }

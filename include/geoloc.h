@@ -67,6 +67,12 @@ extern "C" {
 /* delay_mode */
 #define GEOLOC_DELAY_LINEAR  0   /* two-tap linear fractional delay (default)              */
 #define GEOLOC_DELAY_ROUND   1   /* integer delay round(D), the paper's Eq. (9)            */
+#define GEOLOC_DELAY_SINC    2   /* eight-tap windowed-sinc fractional delay:
+                                    yt[n] = sum_{t=-3}^{4} w_t y_j[n + floor(D) + t],
+                                    w_t = g(t - a) / sum_s g(s - a), a = D - floor(D),
+                                    g(x) = sinc(x) I0(6 sqrt(1 - (x/4)^2)) / I0(6), |x| < 4;
+                                    flat to better than 1e-3 up to a quarter of f_s where the
+                                    two-tap delay loses up to 3 dB                          */
 
 /* accum_mode */
 #define GEOLOC_ACC_POWER     0   /* J = sum |C|^2 */

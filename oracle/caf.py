@@ -26,7 +26,7 @@ from typing import Sequence, Tuple
 
 import numpy as np
 
-from . import geometry, grid_ecef, LINEAR, ROUND, POWER, MAG
+from . import geometry, grid_ecef, sinc_taps, LINEAR, ROUND, SINC, POWER, MAG
 
 
 def bins(nu_lo: float, nu_hi: float, n_bins: int) -> np.ndarray:
@@ -54,7 +54,8 @@ def table(yi: np.ndarray, yj: np.ndarray, k: int, step_len: int, fs: float, lag_
 
 def interp(T: np.ndarray, lag_lo: int, nu_lo: float, dnu: float, D: np.ndarray, nu: np.ndarray,
            delay_mode: int = LINEAR) -> np.ndarray:
-    """Bilinear complex interpolation of one step's table at (D, nu) per point."""
+    """Complex interpolation of one step's table at (D, nu) per point: linear in Doppler,
+    and in lag linear (LINEAR), nearest (ROUND) or the eight windowed-sinc taps (SINC)."""
     if delay_mode == ROUND:
         d0 = np.where(D >= 0, np.floor(np.abs(D) + 0.5), -np.floor(np.abs(D) + 0.5)).astype(np.int64)
         a = np.zeros_like(D)
@@ -72,6 +73,17 @@ def interp(T: np.ndarray, lag_lo: int, nu_lo: float, dnu: float, D: np.ndarray, 
     top = (m0 == M - 1) & (b == 0.0)
     m0 = np.where(top, M - 2, m0)
     b = np.where(top, 1.0, b)
+    if delay_mode == SINC:
+        # eight lag taps (d0 - 3 .. d0 + 4), each interpolated linearly in Doppler
+        if np.any(r0 - 3 < 0) or np.any(r0 + 4 >= nl) or np.any(m0 < 0) or np.any(m0 + 1 >= M):
+            raise ValueError("CAF window does not cover every point")
+        out = np.zeros(D.shape, dtype=np.complex128)
+        for p in range(D.size):
+            w = sinc_taps(float(a.flat[p]))
+            for t in range(8):
+                r = r0.flat[p] - 3 + t
+                out.flat[p] += w[t] * ((1 - b.flat[p]) * T[r, m0.flat[p]] + b.flat[p] * T[r, m0.flat[p] + 1])
+        return out
     topd = (r0 == nl - 1) & (a == 0.0)
     r0 = np.where(topd, nl - 2, r0)
     a = np.where(topd, 1.0, a)

@@ -410,7 +410,11 @@ int caf_prepare(geoloc_plan_t p, const float2* cap, hipStream_t s) {
         return fail(GEOLOC_EINVAL, "geometry out of range for a CAF table (D in [%g, %g], nu in [%g, %g])", dmin,
                     dmax, nmin, nmax);
     // lag window
-    const int64_t need_lo = (int64_t)std::floor(dmin) - 1, need_hi = (int64_t)std::floor(dmax) + 2;
+    // lags the interpolation reads: floor(D) and floor(D) + 1 (LINEAR, ROUND), floor(D) - 3 ..
+    // floor(D) + 4 (SINC), with one lag of margin either side
+    const int64_t tap_lo = p->delay_mode == GEOLOC_DELAY_SINC ? kSincLo : 0;
+    const int64_t tap_hi = p->delay_mode == GEOLOC_DELAY_SINC ? kSincTaps - 1 - kSincLo : 1;
+    const int64_t need_lo = (int64_t)std::floor(dmin) - tap_lo - 1, need_hi = (int64_t)std::floor(dmax) + tap_hi + 1;
     const int64_t n_lags = p->caf_lags_req > 0 ? p->caf_lags_req : need_hi - need_lo + 1;
     int64_t lag_lo = need_lo;
     if (p->caf_lag_lo_set)
@@ -603,7 +607,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     if (d->method != GEOLOC_DIRECT_FP32 && d->method != GEOLOC_CAF_BF16 && d->method != GEOLOC_CAF_FP16 &&
         d->method != GEOLOC_DIRECT_FP32_POINTWISE)
         return fail(GEOLOC_EINVAL, "unknown method %d", d->method);
-    if (d->delay_mode != GEOLOC_DELAY_LINEAR && d->delay_mode != GEOLOC_DELAY_ROUND)
+    if (d->delay_mode != GEOLOC_DELAY_LINEAR && d->delay_mode != GEOLOC_DELAY_ROUND &&
+        d->delay_mode != GEOLOC_DELAY_SINC)
         return fail(GEOLOC_EINVAL, "unknown delay_mode %d", d->delay_mode);
     if (d->accum_mode != GEOLOC_ACC_POWER && d->accum_mode != GEOLOC_ACC_MAG)
         return fail(GEOLOC_EINVAL, "unknown accum_mode %d", d->accum_mode);
@@ -842,6 +847,8 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
         if (p->use_fact)
             HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, s));
+        else if (p->delay_mode == GEOLOC_DELAY_SINC)
+            HIP_TRY(launch_direct_sinc(a, s));
         else
             HIP_TRY(launch_direct(a, p->delay_mode, s));
         if ((rc = span_end(p, s, &sc))) return rc;
@@ -853,7 +860,10 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
             m.mask = p->d_deferred;
             m.load_J = 1;
             if ((rc = span_begin(p, s, &sd, 2))) return rc;
-            HIP_TRY(launch_direct(m, p->delay_mode, s));
+            if (p->delay_mode == GEOLOC_DELAY_SINC)
+                HIP_TRY(launch_direct_sinc(m, s));
+            else
+                HIP_TRY(launch_direct(m, p->delay_mode, s));
             if ((rc = span_end(p, s, &sd))) return rc;
         }
         HIP_TRY(launch_direct_reduce(a, s));

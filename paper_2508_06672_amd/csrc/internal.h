@@ -79,7 +79,45 @@ __device__ inline float2 cis_cycles(double cyc) {
     return make_float2(c, s);
 }
 
+// Windowed-sinc fractional delay (GEOLOC_DELAY_SINC): eight taps t = -3 .. 4 around
+// floor(D), w_t = g(t - alpha) / sum_s g(s - alpha), g(x) = sinc(x) I0(6 sqrt(1 - (x/4)^2)) / I0(6)
+// for |x| < 4. I0 by its power series (20 terms reach FP32 precision for arguments <= 6).
+constexpr int kSincTaps = 8;
+constexpr int kSincLo = 3;     // taps before floor(D)
+
+__device__ inline float bessel_i0f(float x) {
+    const float q = 0.25f * x * x;
+    float term = 1.f, sum = 1.f;
+#pragma unroll
+    for (int k = 1; k <= 20; ++k) {
+        term *= q / (float)(k * k);
+        sum += term;
+    }
+    return sum;
+}
+
+__device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
+    const float inv_i0 = 1.f / bessel_i0f(6.f);
+    float sum = 0.f;
+#pragma unroll
+    for (int t = 0; t < kSincTaps; ++t) {
+        const float x = (float)(t - kSincLo) - alpha;
+        float g = 0.f;
+        if (fabsf(x) < 4.f) {
+            const float sn = x == 0.f ? 1.f : sinpif(x) / (3.14159265358979f * x);
+            const float u = 0.25f * x;
+            g = sn * bessel_i0f(6.f * sqrtf(fmaxf(1.f - u * u, 0.f))) * inv_i0;
+        }
+        w[t] = g;
+        sum += g;
+    }
+    const float inv = 1.f / sum;
+#pragma unroll
+    for (int t = 0; t < kSincTaps; ++t) w[t] *= inv;
+}
+
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s);
+hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
 
 constexpr int32_t kMaxItemGroups = 64;
 int32_t direct_groups(int64_t n_tiles, int64_t n_items);   // n_items = pairs x steps per chunk

@@ -21,7 +21,8 @@
 //   k_caf_gemm    MFMA complex GEMM, lag products formed in the prologue from LDS-staged
 //                 samples (never written to HBM), FP32 accumulation, optional split-K
 //   k_caf_reduce  sums split-K partials and undoes the input scale
-//   k_caf_interp  FP64 geometry inline, bilinear complex interpolation, J += |C|^2
+//   k_caf_interp  FP64 geometry inline, complex interpolation (linear in Doppler; linear,
+//                 nearest or eight windowed-sinc taps in lag), J += |C|^2
 //
 // MFMA: v_mfma_f32_32x32x16_{bf16,f16}. Lane l holds A[l % 32][8 (l / 32) + j] and
 // B[8 (l / 32) + j][l % 32], j < 8; accumulator i of lane l is C[8 (i / 4) + 4 (l / 32) +
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(256) void k_caf_reduce(const float2* __restrict__ p
 
 // --------------------------------------------------------------------------- interpolation
 
-template <bool kRound>
+template <int kMode>   // GEOLOC_DELAY_LINEAR, _ROUND or _SINC
 __global__ __launch_bounds__(256) void k_caf_interp(CafInterpArgs a) {
     const int tid = threadIdx.x;
     bool valid;
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void k_caf_interp(CafInterpArgs a) {
             if (!(fabs(D) < 1.0e9)) D = 1.0e9;
             int64_t d0;
             double al;
-            if constexpr (kRound) {
+            if constexpr (kMode == GEOLOC_DELAY_ROUND) {
                 d0 = (int64_t)round(D);
                 al = 0.0;
             } else {
@@ -309,25 +310,45 @@ __global__ __launch_bounds__(256) void k_caf_interp(CafInterpArgs a) {
             const double mf = floor(u);
             int64_t m0 = (int64_t)mf;
             double be = u - mf;
-            int64_t r0 = d0 - a.lag_lo;
             if (m0 == a.M - 1 && be == 0.0) {
                 m0 = a.M - 2;
                 be = 1.0;
             }
-            if (r0 == a.n_lags - 1 && al == 0.0) {
-                r0 = a.n_lags - 2;
-                al = 1.0;
-            }
-            // the host checked coverage; clamping only keeps every read inside the table
-            r0 = min(max(r0, (int64_t)0), (int64_t)a.n_lags - 2);
             m0 = min(max(m0, (int64_t)0), (int64_t)a.M - 2);
             const float2* T = a.T + ((int64_t)e * a.kc + kk) * (int64_t)a.n_lags_pad * a.M_pad;
-            const float2 t00 = T[r0 * a.M_pad + m0], t01 = T[r0 * a.M_pad + m0 + 1];
-            const float2 t10 = T[(r0 + 1) * a.M_pad + m0], t11 = T[(r0 + 1) * a.M_pad + m0 + 1];
-            const float fa = (float)al, fb = (float)be;
-            const float w00 = (1.f - fa) * (1.f - fb), w10 = fa * (1.f - fb), w01 = (1.f - fa) * fb, w11 = fa * fb;
-            const float cr = w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x;
-            const float ci = w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y;
+            const float fb = (float)be;
+            float cr, ci;
+            if constexpr (kMode == GEOLOC_DELAY_SINC) {
+                // eight lag taps floor(D) - 3 .. floor(D) + 4, each linear in Doppler
+                float w[kSincTaps];
+                sinc_taps((float)al, w);
+                int64_t r0 = d0 - kSincLo - a.lag_lo;
+                // the host checked coverage; clamping only keeps every read inside the table
+                r0 = min(max(r0, (int64_t)0), (int64_t)a.n_lags - kSincTaps);
+                cr = 0.f;
+                ci = 0.f;
+#pragma unroll
+                for (int t = 0; t < kSincTaps; ++t) {
+                    const float2 v0 = T[(r0 + t) * a.M_pad + m0], v1 = T[(r0 + t) * a.M_pad + m0 + 1];
+                    cr = fmaf(w[t], fmaf(fb, v1.x - v0.x, v0.x), cr);
+                    ci = fmaf(w[t], fmaf(fb, v1.y - v0.y, v0.y), ci);
+                }
+            } else {
+                int64_t r0 = d0 - a.lag_lo;
+                if (r0 == a.n_lags - 1 && al == 0.0) {
+                    r0 = a.n_lags - 2;
+                    al = 1.0;
+                }
+                // the host checked coverage; clamping only keeps every read inside the table
+                r0 = min(max(r0, (int64_t)0), (int64_t)a.n_lags - 2);
+                const float2 t00 = T[r0 * a.M_pad + m0], t01 = T[r0 * a.M_pad + m0 + 1];
+                const float2 t10 = T[(r0 + 1) * a.M_pad + m0], t11 = T[(r0 + 1) * a.M_pad + m0 + 1];
+                const float fa = (float)al;
+                const float w00 = (1.f - fa) * (1.f - fb), w10 = fa * (1.f - fb), w01 = (1.f - fa) * fb,
+                            w11 = fa * fb;
+                cr = w00 * t00.x + w10 * t10.x + w01 * t01.x + w11 * t11.x;
+                ci = w00 * t00.y + w10 * t10.y + w01 * t01.y + w11 * t11.y;
+            }
             const double pw = (double)cr * cr + (double)ci * ci;
             jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
         }
@@ -381,9 +402,11 @@ hipError_t launch_caf_reduce(const float2* part, int64_t n, int32_t n_split, flo
 hipError_t launch_caf_interp(const CafInterpArgs& a, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.tiling.tiles_x * a.tiling.tiles_y));
     if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL(k_caf_interp<true>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_caf_interp<GEOLOC_DELAY_ROUND>, grid, dim3(256), 0, s, a);
+    else if (delay_mode == GEOLOC_DELAY_SINC)
+        hipLaunchKernelGGL(k_caf_interp<GEOLOC_DELAY_SINC>, grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_caf_interp<false>, grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_caf_interp<GEOLOC_DELAY_LINEAR>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -114,14 +114,15 @@ struct FactStep {
     double cyc;            // this lane's FDOA in cycles per sample
     float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
     float alpha;           // this lane's fractional lag
+    float w[kSincTaps];    // this lane's windowed-sinc weights (SINC only)
     float c1, c2, c3;      // Taylor coefficients of the lane's Doppler deviation
-    int dlo, Hs, NB, TB;   // lowest lag, lag stride of s_G (even), blocks per round / per LDS tile
+    int dlo, Hs, NB, TB;   // lowest lag read, lag stride of s_G (even), blocks per round / per LDS tile
     int my_b, my_l, off;   // this thread's (block, lag pair) item; this lane's lag offset
 };
 
 // One (tile, step): stage samples, then per round of NB blocks form the lag moments
 // (phase 1) and combine them per point (phase 2). Adds the step's C into (cr, ci).
-template <bool kRound, int Q>
+template <int kMode, int Q>
 __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
                           const FactStep& st, float2* s_y, float2* s_v, float2* s_G, const float2* s_rot, float& cr,
                           float& ci) {
@@ -170,13 +171,25 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                 float m[Q][2];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    const float2 g0 = g[q * Hs];
-                    m[q][0] = g0.x;
-                    m[q][1] = g0.y;
-                    if constexpr (!kRound) {
-                        const float2 g1 = g[q * Hs + 1];
-                        m[q][0] = fmaf(st.alpha, g1.x - g0.x, g0.x);
-                        m[q][1] = fmaf(st.alpha, g1.y - g0.y, g0.y);
+                    if constexpr (kMode == GEOLOC_DELAY_SINC) {
+                        float mr = 0.f, mi = 0.f;
+#pragma unroll
+                        for (int t = 0; t < kSincTaps; ++t) {
+                            const float2 gt = g[q * Hs + t];
+                            mr = fmaf(st.w[t], gt.x, mr);
+                            mi = fmaf(st.w[t], gt.y, mi);
+                        }
+                        m[q][0] = mr;
+                        m[q][1] = mi;
+                    } else {
+                        const float2 g0 = g[q * Hs];
+                        m[q][0] = g0.x;
+                        m[q][1] = g0.y;
+                        if constexpr (kMode == GEOLOC_DELAY_LINEAR) {
+                            const float2 g1 = g[q * Hs + 1];
+                            m[q][0] = fmaf(st.alpha, g1.x - g0.x, g0.x);
+                            m[q][1] = fmaf(st.alpha, g1.y - g0.y, g0.y);
+                        }
                     }
                 }
                 // s = m0 + j c1 m1 + c2 m2 + j c3 m3
@@ -204,7 +217,7 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
     }
 }
 
-template <bool kRound>
+template <int kMode>   // GEOLOC_DELAY_LINEAR, _ROUND or _SINC
 __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     __shared__ float2 s_y[kFT + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         if (!(fabs(D) < 1.0e9)) D = 1.0e9;
         int d0;
         float alpha;
-        if constexpr (kRound) {
+        if constexpr (kMode == GEOLOC_DELAY_ROUND) {
             d0 = (int)round(D);
             alpha = 0.f;
         } else {
@@ -269,23 +282,27 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
                 }
             }
         }
-        const bool fact = Q > 0 && spread + 2 <= kFH;
+        // lags read per point: floor(D) .. floor(D) + 1, or floor(D) - 3 .. floor(D) + 4 (SINC)
+        constexpr int kTaps = kMode == GEOLOC_DELAY_SINC ? kSincTaps : 2;
+        constexpr int kTapLo = kMode == GEOLOC_DELAY_SINC ? kSincLo : 0;
+        const bool fact = Q > 0 && spread + kTaps <= kFH;
         if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
         if (!fact) continue;                           // uniform: the per-point kernel takes it
 
         FactStep st;
-        const int H = (int)spread + 2;
+        const int H = (int)spread + kTaps;
         const int Hg = (H + 1) / 2;                    // lag pairs
         st.n_step = (int64_t)(a.k0 + kk) * a.L;
         st.cyc = cyc;
         st.ERB = cis_cycles(cyc * (double)kFB);
         st.alpha = alpha;
+        if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(alpha, st.w);
         // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
         const float dl = (float)(two_pi * cyc - (double)tbar);
         st.c1 = dl;
         st.c2 = -0.5f * dl * dl;
         st.c3 = -dl * dl * dl * (1.f / 6.f);
-        st.dlo = dlo;
+        st.dlo = dlo - kTapLo;
         st.Hs = 2 * Hg;
         st.NB = min(kFTB, 256 / Hg);
         st.TB = st.NB * (kFTB / st.NB);
@@ -299,10 +316,10 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         }
         float cr = 0.f, ci = 0.f;
         switch (Q) {
-            case 1: fact_step<kRound, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 2: fact_step<kRound, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 3: fact_step<kRound, (kFQ < 3 ? kFQ : 3)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            default: fact_step<kRound, kFQ>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 1: fact_step<kMode, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 2: fact_step<kMode, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kMode, (kFQ < 3 ? kFQ : 3)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kMode, kFQ>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
         }
         const double pw = (double)cr * cr + (double)ci * ci;
         jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
@@ -317,9 +334,11 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL(k_direct_fact<true>, grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_ROUND>, grid, block, 0, s, a, deferred);
+    else if (delay_mode == GEOLOC_DELAY_SINC)
+        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_SINC>, grid, block, 0, s, a, deferred);
     else
-        hipLaunchKernelGGL(k_direct_fact<false>, grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_LINEAR>, grid, block, 0, s, a, deferred);
     return hipGetLastError();
 }
 

@@ -1,0 +1,97 @@
+// k_direct_sinc.hip -- Eq. (11) point by point with the eight-tap windowed-sinc delay
+// (GEOLOC_DELAY_SINC): the kernel of GEOLOC_DIRECT_FP32_POINTWISE in that mode, and the
+// pass over the (tile, step) pairs the factored kernel defers.
+//
+// One lane per point, one workgroup per tile of 256 points and group of (pair, step)
+// items, as in the other correlation kernels (same tiling, masks and partial rows). Per
+// sample a lane reads y_i[n] (the same address for every lane: one broadcast load) and the
+// eight taps y_j[n + floor(D) - 3 .. n + floor(D) + 4] from global memory; the taps slide in
+// registers, so each sample loads one new y_j value. The Doppler phasor advances by a
+// per-lane step and is re-anchored from an exact FP64 phase every 64 samples.
+#include "internal.h"
+
+namespace geoloc {
+
+constexpr int kSincAnchor = 64;   // samples between FP64 phase re-anchors
+
+__global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x % a.n_tiles;
+    const int group = (int)(blockIdx.x / a.n_tiles);
+    const int64_t n_items = (int64_t)a.n_pairs * a.kc;
+    const int64_t it_lo = n_items * group / a.n_groups;
+    const int64_t it_hi = n_items * (group + 1) / a.n_groups;
+    bool valid;
+    const int64_t p = tile_point(a.tiling, tile, tid, &valid);
+    double jacc = 0.0;
+    if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
+    if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
+    const double centre = 0.5 * (double)(a.L - 1);
+
+    for (int64_t it = it_lo; it < it_hi; ++it) {
+        const int e = (int)(it / a.kc);
+        const int kk = (int)(it - (int64_t)e * a.kc);
+        // with a mask, only the (tile, step) pairs the factored kernel left over
+        if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
+        if (!valid) continue;
+        const int2 pr = a.pairs[e];
+        const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
+        const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
+        const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
+        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
+        double D = a.D[gi];
+        const double nu = a.nu[gi];
+        if (!(fabs(D) < 1.0e9)) D = 1.0e9;
+        const double f = floor(D);
+        const int64_t d0 = (int64_t)f;
+        float w[kSincTaps];
+        sinc_taps((float)(D - f), w);
+        const double cyc = nu * a.inv_fs;
+        const float2 E = cis_cycles(cyc);
+        // sliding window of the eight taps for sample n: y_j[n + d0 - 3 + t]
+        auto yj_at = [&](int64_t m) { return (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f); };
+        float2 win[kSincTaps];
+#pragma unroll
+        for (int t = 0; t < kSincTaps - 1; ++t) win[t + 1] = yj_at(n_step + d0 - kSincLo + t);
+        float cr = 0.f, ci = 0.f;
+        for (int s0 = 0; s0 < a.L; s0 += kSincAnchor) {
+            float2 W = cis_cycles(cyc * ((double)s0 - centre));
+            const int s1 = min(a.L, s0 + kSincAnchor);
+            for (int n = s0; n < s1; ++n) {
+#pragma unroll
+                for (int t = 0; t < kSincTaps - 1; ++t) win[t] = win[t + 1];
+                win[kSincTaps - 1] = yj_at(n_step + n + d0 - kSincLo + kSincTaps - 1);
+                float yr = 0.f, yim = 0.f;
+#pragma unroll
+                for (int t = 0; t < kSincTaps; ++t) {
+                    yr = fmaf(w[t], win[t].x, yr);
+                    yim = fmaf(w[t], win[t].y, yim);
+                }
+                const float2 x = yi[n_step + n];
+                // x * conj(yt) * W
+                const float pr_ = fmaf(x.x, yr, x.y * yim);
+                const float pi_ = fmaf(x.y, yr, -(x.x * yim));
+                cr = fmaf(pr_, W.x, fmaf(-pi_, W.y, cr));
+                ci = fmaf(pr_, W.y, fmaf(pi_, W.x, ci));
+                const float wr = fmaf(W.x, E.x, -(W.y * E.y));
+                W.y = fmaf(W.x, E.y, W.y * E.x);
+                W.x = wr;
+            }
+        }
+        const double pw = (double)cr * cr + (double)ci * ci;
+        jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
+    }
+    if (!valid) return;
+    if (a.n_groups == 1)
+        a.J[p] = (float)jacc;
+    else
+        a.partial[(int64_t)group * a.P + p] = jacc;
+}
+
+hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s) {
+    dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
+    hipLaunchKernelGGL(k_direct_sinc, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace geoloc

@@ -21,7 +21,7 @@ ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
-DELAY_LINEAR, DELAY_ROUND = 0, 1
+DELAY_LINEAR, DELAY_ROUND, DELAY_SINC = 0, 1, 2
 ACC_POWER, ACC_MAG = 0, 1
 GRID_RECT, GRID_POINTS = 0, 1
 ACCUMULATE = 1

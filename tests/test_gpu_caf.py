@@ -147,3 +147,22 @@ def test_caf_1e6_map_agrees_with_direct(torch, G):
         f"argmax {ac} vs {ad}")
     assert _cell_dist(ac, ad, wl.n_cols) <= 1 or Jd[ac] >= (1 - 2 * CAF_TOL) * Jd[ad]
     assert e <= 5e-2
+
+
+def test_caf_sinc_delay(torch, G):
+    """The CAF map read with the eight windowed-sinc lag taps (BF16 and FP16) against the
+    FP64 CAF oracle with the same window and taps, and the FP32 direct SINC map."""
+    wl = configs.CAF_SMALL
+    scn = sim.make_scenario(wl, 5)
+    caps = torch.from_numpy(scn.captures).cuda()
+    la, lo_ = sim.points_of(scn)
+    Jd = oracle.map_scenario(scn, delay_mode=oracle.SINC)
+    for m in (G.CAF_BF16, G.CAF_FP16):
+        with G.Plan.for_scenario(scn, method=m, delay_mode=G.DELAY_SINC) as plan:
+            Jg = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+            lag_lo, n_lags, lo, hi, M = _window(plan.info())
+        Jo = ocaf.caf_map_points(la, lo_, scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz, list(wl.pairs),
+                                 lag_lo, n_lags, lo, hi, M, delay_mode=oracle.SINC)
+        log(f"caf sinc method {m}: err vs CAF oracle {err_J(Jg, Jo):.3g}, vs direct {err_J(Jg, Jd):.3g}")
+        assert err_J(Jg, Jo) <= CAF_TOL
+        assert err_J(Jo, Jd) <= 1e-2

@@ -230,3 +230,42 @@ def test_sheared_tiles_match_oracle(torch, G):
         assert e <= DIRECT_TOL
         check_argmax(Jg, Jo, DIRECT_TOL)
     assert any(sh != 0 for sh, _ in shears) and len(shears) == 2
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+def test_sinc_delay_factored_and_pointwise(torch, G, accum):
+    """The eight-tap windowed-sinc delay on the small workload (tile-factored kernel) and
+    on the same grid with the per-point kernel, against the oracle in SINC mode."""
+    scn = sim.make_scenario(configs.SMALL.with_(n_samples=12000), 21)
+    log(f"sinc delay accum={accum}")
+    Jo = oracle.map_scenario(scn, delay_mode=oracle.SINC, accum_mode=accum)
+    for method in (G.DIRECT_FP32, G.DIRECT_FP32_POINTWISE):
+        Jg = _gpu_map(torch, G, scn, delay_mode=G.DELAY_SINC, accum_mode=accum, method=method)
+        e = err_J(Jg, Jo)
+        log(f"  method {method}: err_J = {e:.3g}")
+        assert e <= DIRECT_TOL
+        check_argmax(Jg, Jo, DIRECT_TOL)
+
+
+def test_sinc_delay_wide_tiles_and_point_list(torch, G):
+    """SINC on 8 km cells (every tile-step deferred to the per-point SINC kernel) and on a
+    scattered point list at 10 MHz, against the oracle."""
+    wl = configs.MAP_1E6.with_(n_rows=37, n_cols=41, spacing_m=8000.0, n_samples=30_000)
+    scn = sim.make_scenario(wl, 22)
+    log("sinc wide tiles")
+    Jo = oracle.map_scenario(scn, delay_mode=oracle.SINC)
+    Jg = _gpu_map(torch, G, scn, delay_mode=G.DELAY_SINC)
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+    wl = configs.MAP_1E6.with_(n_samples=20_000, step_len=10_000)
+    scn = sim.make_scenario(wl, 23)
+    la, lo = sim.points_of(scn)
+    rng = np.random.Generator(np.random.PCG64(23))
+    sel = rng.choice(la.size, 700, replace=False)
+    log("sinc point list")
+    Jo = oracle.map_points(la[sel], lo[sel], scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz,
+                           delay_mode=oracle.SINC)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan(n_rx=2, n_samples=wl.n_samples, step_len=wl.step_len, fs_hz=wl.fs_hz, fc_hz=wl.fc_hz,
+                lat=la[sel], lon=lo[sel], grid_kind=G.GRID_POINTS, delay_mode=G.DELAY_SINC) as plan:
+        Jg = plan.map(caps, scn.states).cpu().numpy()
+    assert err_J(Jg, Jo) <= DIRECT_TOL

@@ -454,3 +454,20 @@ def test_p16_sinc_delay_recovers_a_fractionally_delayed_band_limited_signal():
         if abs(a - 0.5) < 1e-9:
             assert np.min(np.abs(G)) < 0.74          # about -2.7 dB at 0.24 of the sample rate
         assert full > 0
+
+
+def test_p16_sinc_caf_on_bin_equals_direct():
+    """Eq. (11) with the windowed-sinc delay is linear in y_j, so the CAF table read with the
+    same eight taps reproduces the direct SINC correlation whenever nu falls on a bin."""
+    rng = _rng(161)
+    N, L, fs = 3000, 1000, 1.0e6
+    yi, yj = _cn(rng, N), _cn(rng, N)
+    nu_b = caf.bins(-900.0, 600.0, 16)
+    lag_lo, n_lags = -12, 30
+    for k in range(3):
+        T = caf.table(yi, yj, k, L, fs, lag_lo, n_lags, nu_b)
+        for D, m in ((3.37, 4), (-5.81, 11), (0.5, 0), (7.0, 15)):
+            c_dir = oracle.corr(yi, yj, k, L, D, nu_b[m], fs, oracle.SINC)
+            dnu = nu_b[1] - nu_b[0]
+            c_caf = caf.interp(T, lag_lo, nu_b[0], dnu, np.array([D]), np.array([nu_b[m]]), oracle.SINC)[0]
+            assert abs(c_caf - c_dir) <= 1e-9 * max(1.0, abs(c_dir)), (k, D, m)
