@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GEOLOC_ABI_VERSION 2
+#define GEOLOC_ABI_VERSION 3
 
 /* status codes */
 #define GEOLOC_OK            0
@@ -143,6 +143,10 @@ typedef struct geoloc_plan_info {
     int32_t tile_rows, tile_cols;   /* workgroup tile of the last map: rows x cells per row */
     int32_t tile_shear;        /* column shift per tile row (diagonal tiles)              */
     int32_t tile_transpose;    /* 1: rows and columns swap roles in the tile              */
+    int32_t step_segments;     /* direct method: coherent segments each step is split into
+                                  across workgroups (1 = not split); their complex partial
+                                  sums are added before |C|^2 is taken                   */
+    int32_t segment_len;       /* samples per segment (step_len when not split)          */
 } geoloc_plan_info;
 
 /* ABI version of the loaded library (GEOLOC_ABI_VERSION when it matches). */

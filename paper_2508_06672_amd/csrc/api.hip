@@ -72,6 +72,9 @@ struct geoloc_plan_s {
     int32_t n_groups = 1;
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
     bool use_fact = false;           // factored direct kernel (method GEOLOC_DIRECT_FP32)
+    bool fact_wide = false;          // its variant with up to 6 Taylor terms (wide Doppler spreads)
+    int32_t n_segs = 1, seg_len = 0; // factored kernel: coherent segments per step (few tiles, long steps)
+    float2* d_cpart = nullptr;       // [n_segs][n_pairs * kc][P] complex partial sums
     ArgmaxScratch am;
     int64_t device_bytes = 0;
     // host staging for receiver states (pinned) and its reuse guard
@@ -146,6 +149,7 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->d_D);
     (void)hipFree(p->d_nu);
     (void)hipFree(p->d_partial);
+    (void)hipFree(p->d_cpart);
     (void)hipFree(p->d_deferred);
     (void)hipFree(p->am.part_val);
     (void)hipFree(p->am.part_idx);
@@ -251,9 +255,12 @@ void host_delay_doppler(const geoloc_plan_s* p, double lat, double lon, const do
 // correlation summed over the pairs, counting the lanes its tiles leave outside the grid.
 // The lag moments cost about (8 + 4Q) / NB instructions per correlation (NB blocks per
 // round, from the lag spread H) and the per-point combination (6Q + 8) / 64; a tile that
-// the factored kernel would defer costs about 13.
+// the factored kernel would defer costs about 13. Taylor orders 5 and 6 need the kernel's
+// wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
+// are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
 void choose_tiling(geoloc_plan_t p, const double* states) {
     p->tiling = p->base_tiling;
+    p->fact_wide = false;
     if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 || p->tile_shapes.empty()) return;
     const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
     const int64_t ra = std::max<int64_t>(r0 - 1, 0), rb = std::min<int64_t>(r0 + 1, p->rows - 1);
@@ -280,8 +287,9 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         if (!std::isfinite(g[0] + g[1] + g[2] + g[3])) return;
         grads.push_back(g);
     }
-    auto cost = [&](const PointTiling& t) {
+    auto cost = [&](const PointTiling& t, int* q_need) {
         double total = 0.0;
+        *q_need = 0;
         for (const auto& g : grads) {
             const double gr = t.transpose ? g[1] : g[0], gc = t.transpose ? g[0] : g[1];
             const double hr = t.transpose ? g[3] : g[2], hc = t.transpose ? g[2] : g[3];
@@ -290,7 +298,7 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
                 0.5 * (std::fabs(hr + t.shear * hc) * (t.tile_h - 1) + std::fabs(hc) * (t.tile_w - 1)) * 32.0;
             int Q = 0;
             double term = 1.0;
-            for (int q = 1; q <= 4 && xr < 1.0; ++q) {
+            for (int q = 1; q <= 6 && xr < 1.0; ++q) {
                 term *= xr / q;
                 if (term <= 5.9604645e-8) {
                     Q = q;
@@ -301,20 +309,24 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             if (Q > 0 && H <= 128.0) {
                 const int Hg = (int)std::ceil(H / 2.0);
                 const int NB = std::min(32, 256 / Hg);
-                c = (8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0;
+                c = ((8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0) * (Q > 4 ? 1.5 : 1.0);
+                *q_need = std::max(*q_need, Q);
             }
             total += c;
         }
         return total * (double)(t.tiles_x * t.tiles_y * kTilePoints) / (double)p->P;
     };
-    double best = cost(p->base_tiling);
+    int q_best = 0, q = 0;
+    double best = cost(p->base_tiling, &q_best);
     for (const auto& t : p->tile_shapes) {
-        const double c = cost(t);
+        const double c = cost(t, &q);
         if (c < 0.97 * best) {
             best = c;
+            q_best = q;
             p->tiling = t;
         }
     }
+    p->fact_wide = q_best > 4;
 }
 
 int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc, double* D, double* nu,
@@ -727,9 +739,24 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
         if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
         if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
-        p->n_groups = direct_groups(p->base_tiling.tiles_x * p->base_tiling.tiles_y, (int64_t)p->kc * p->n_pairs);
-        if (p->n_groups > 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P))) break;
         p->use_fact = p->method == GEOLOC_DIRECT_FP32;
+        const int64_t base_tiles = p->base_tiling.tiles_x * p->base_tiling.tiles_y;
+        const int64_t items = (int64_t)p->kc * p->n_pairs;
+        p->n_groups = direct_groups(base_tiles, items);
+        const int64_t wgs = base_tiles * p->n_groups;
+        if (p->use_fact && wgs < 1024 && p->L >= 8192) {
+            // too few (tile, item group) workgroups to fill the GPU, and long steps: also
+            // split every step into coherent segments of whole 2,048-sample LDS tiles
+            int64_t ns = std::min<int64_t>({(1024 + wgs - 1) / wgs, 16, p->L / 2048});
+            if (ns >= 2) {
+                const int64_t len = round_up((p->L + ns - 1) / ns, 2048);
+                p->seg_len = (int32_t)len;
+                p->n_segs = (int32_t)((p->L + len - 1) / len);
+                if ((rc = dev_alloc(p, &p->d_cpart, (size_t)p->n_segs * items * P))) break;
+            }
+        }
+        if (p->n_groups > 1 && p->n_segs <= 1 && (rc = dev_alloc(p, &p->d_partial, (size_t)p->n_groups * P)))
+            break;
         if (p->use_fact &&
             (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->max_tiles)))
             break;
@@ -844,10 +871,18 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.n_groups = (int32_t)std::min<int64_t>(p->n_groups, (int64_t)kc * p->n_pairs);
         a.partial = p->d_partial;
         a.mask = nullptr;
+        a.n_segs = p->use_fact ? p->n_segs : 1;
+        a.seg_len = p->seg_len;
+        a.cpart = p->d_cpart;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
-        if (p->use_fact)
-            HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, s));
-        else if (p->delay_mode == GEOLOC_DELAY_SINC)
+        if (p->use_fact) {
+            HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, p->fact_wide, s));
+            if (a.n_segs > 1) {
+                // the segment reduction writes J itself: later passes add to it in place
+                HIP_TRY(launch_direct_seg_reduce(a, s));
+                a.n_groups = 1;
+            }
+        } else if (p->delay_mode == GEOLOC_DELAY_SINC)
             HIP_TRY(launch_direct_sinc(a, s));
         else
             HIP_TRY(launch_direct(a, p->delay_mode, s));
@@ -972,6 +1007,8 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.tile_cols = p->tiling.tile_w;
     r.tile_shear = p->tiling.shear;
     r.tile_transpose = p->tiling.transpose;
+    r.step_segments = p->n_segs > 1 ? p->n_segs : 1;
+    r.segment_len = p->n_segs > 1 ? p->seg_len : (int32_t)p->L;
     *out = r;
     return GEOLOC_OK;
 }

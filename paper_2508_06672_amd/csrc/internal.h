@@ -69,6 +69,10 @@ struct DirectArgs {
     int32_t n_groups;        // groups of (pair, step) items per chunk (1: each workgroup owns its points' J)
     double* partial;         // [n_groups][P] partial sums when n_groups > 1
     const uint8_t* mask;     // [n_pairs][kc][n_tiles]: nonzero = this kernel handles it; NULL = all
+    // factored kernel only: each step split into n_segs coherent segments of seg_len samples
+    // (a multiple of 64) whose complex sums go to cpart [n_segs][n_pairs * kc][P]; 1 = off
+    int32_t n_segs, seg_len;
+    float2* cpart;
 };
 
 // exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
@@ -116,8 +120,11 @@ __device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
     for (int t = 0; t < kSincTaps; ++t) w[t] *= inv;
 }
 
-hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s);
+hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
+                              hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
+// J[p] = (J[p] if loading) + sum over items of |sum over segments of cpart|^2 (or |.|)
+hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s);
 
 constexpr int32_t kMaxItemGroups = 64;
 int32_t direct_groups(int64_t n_tiles, int64_t n_items);   // n_items = pairs x steps per chunk

@@ -19,23 +19,30 @@ constexpr int kCnnMaxCh = 32;
 __device__ inline float act(float v, bool relu) { return (relu && v < 0.f) ? 0.f : v; }
 
 // z[b][o][p] = bias[o] + sum_{c,dy,dx} W[o][c][dy][dx] act(in[b][c][p + (dy-1, dx-1)]).
-// One thread per output pixel computes every output channel; weights sit in LDS as FP32.
+// One thread per output pixel and group of kCnnOG output channels (blockIdx.z), so a
+// single image still spreads over several workgroups; the group's weights sit in LDS as
+// FP32 ordered [c][dy][dx][o], so that one 16-byte read fetches four output channels.
+constexpr int kCnnOG = 8;
+
 template <bool kReluIn>
 __global__ __launch_bounds__(256) void k_cnn_conv_fwd(const float* __restrict__ in, const _Float16* __restrict__ w,
                                                       const _Float16* __restrict__ bias, float* __restrict__ out,
                                                       int C, int O, int H, int W) {
-    __shared__ float s_w[kCnnMaxCh * kCnnMaxCh * 9];
-    __shared__ float s_b[kCnnMaxCh];
-    for (int i = threadIdx.x; i < O * C * 9; i += 256) s_w[i] = (float)w[i];
-    if (threadIdx.x < O) s_b[threadIdx.x] = (float)bias[threadIdx.x];
+    __shared__ __align__(16) float s_w[kCnnMaxCh * 9 * kCnnOG];
+    const int o0 = blockIdx.z * kCnnOG;
+    const int og = min(kCnnOG, O - o0);            // output channels of this group
+    for (int i = threadIdx.x; i < C * 9 * kCnnOG; i += 256) {
+        const int oo = i % kCnnOG, ck = i / kCnnOG; // ck = c * 9 + dy * 3 + dx
+        s_w[i] = oo < og ? (float)w[(int64_t)(o0 + oo) * C * 9 + ck] : 0.f;
+    }
     __syncthreads();
     const int b = blockIdx.y;
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= H * W) return;
     const int h = pix / W, x = pix - h * W;
-    float acc[kCnnMaxCh];
+    float acc[kCnnOG];
 #pragma unroll
-    for (int o = 0; o < kCnnMaxCh; ++o) acc[o] = (o < O) ? s_b[o] : 0.f;
+    for (int oo = 0; oo < kCnnOG; ++oo) acc[oo] = oo < og ? (float)bias[o0 + oo] : 0.f;
     const float* src = in + (int64_t)b * C * H * W;
     for (int c = 0; c < C; ++c) {
 #pragma unroll
@@ -46,17 +53,22 @@ __global__ __launch_bounds__(256) void k_cnn_conv_fwd(const float* __restrict__ 
                 const int ww = x + dx - 1;
                 float v = 0.f;
                 if (hh >= 0 && hh < H && ww >= 0 && ww < W) v = act(src[((int64_t)c * H + hh) * W + ww], kReluIn);
-                const float* wp = s_w + c * 9 + dy * 3 + dx;
+                const float4* wp = reinterpret_cast<const float4*>(s_w + (c * 9 + dy * 3 + dx) * kCnnOG);
 #pragma unroll
-                for (int o = 0; o < kCnnMaxCh; ++o)
-                    if (o < O) acc[o] = fmaf(wp[o * C * 9], v, acc[o]);
+                for (int q = 0; q < kCnnOG / 4; ++q) {
+                    const float4 w4 = wp[q];
+                    acc[4 * q + 0] = fmaf(w4.x, v, acc[4 * q + 0]);
+                    acc[4 * q + 1] = fmaf(w4.y, v, acc[4 * q + 1]);
+                    acc[4 * q + 2] = fmaf(w4.z, v, acc[4 * q + 2]);
+                    acc[4 * q + 3] = fmaf(w4.w, v, acc[4 * q + 3]);
+                }
             }
         }
     }
     float* dst = out + (int64_t)b * O * H * W;
 #pragma unroll
-    for (int o = 0; o < kCnnMaxCh; ++o)
-        if (o < O) dst[(int64_t)o * H * W + pix] = acc[o];
+    for (int oo = 0; oo < kCnnOG; ++oo)
+        if (oo < og) dst[(int64_t)(o0 + oo) * H * W + pix] = acc[oo];
 }
 
 // gin[b][c][p] = mask(zprev[b][c][p] > 0) * sum_{o,dy,dx} W[o][c][2-dy][2-dx] g[b][o][p + (dy-1, dx-1)]
@@ -313,7 +325,7 @@ __global__ __launch_bounds__(256) void k_cnn_prep(const float* __restrict__ J, c
 
 hipError_t launch_cnn_conv_fwd(bool relu_in, const float* in, const _Float16* w, const _Float16* b, float* out, int B,
                                int C, int O, int H, int W, hipStream_t s) {
-    dim3 grid((unsigned)((H * W + 255) / 256), (unsigned)B);
+    dim3 grid((unsigned)((H * W + 255) / 256), (unsigned)B, (unsigned)((O + kCnnOG - 1) / kCnnOG));
     if (relu_in)
         hipLaunchKernelGGL(k_cnn_conv_fwd<true>, grid, dim3(256), 0, s, in, w, b, out, C, O, H, W);
     else

@@ -24,7 +24,8 @@
 // a wave read different banks. The step body is compiled per Taylor order. Q is chosen
 // per tile and step so that the Taylor remainder bound is at most one FP32 unit roundoff
 // (2^-24) of the block's magnitude sum, below the rounding of the block sum itself; a tile
-// whose lag spread exceeds kFH or whose Doppler spread needs more than kFQ terms is flagged
+// whose lag spread exceeds kFH or whose Doppler spread needs more Taylor terms than the
+// variant carries (4, or 6 in the variant the host picks for wide Doppler spreads) is flagged
 // in `deferred` and left to the per-point kernel, which then adds that step into J.
 #include "internal.h"
 
@@ -37,12 +38,10 @@ constexpr int kFB = 64;          // samples per moment block
 #ifndef GEOLOC_FACT_TB
 #define GEOLOC_FACT_TB 32
 #endif
-#ifndef GEOLOC_FACT_Q
-#define GEOLOC_FACT_Q 4
-#endif
 constexpr int kFTB = GEOLOC_FACT_TB;   // most blocks per LDS tile
 constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
-constexpr int kFQ = GEOLOC_FACT_Q;     // most Taylor terms
+constexpr int kFQ = 4;           // most Taylor terms of the default variant
+constexpr int kFQWide = 6;       // most Taylor terms of the variant for wide Doppler spreads
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
 constexpr int kFVS = kFB + 2;    // LDS stride of the reference samples of one block
 constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
@@ -115,9 +114,12 @@ struct FactStep {
     float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
     float alpha;           // this lane's fractional lag
     float w[kSincTaps];    // this lane's windowed-sinc weights (SINC only)
-    float c1, c2, c3;      // Taylor coefficients of the lane's Doppler deviation
+    float c[kFQWide];      // Taylor coefficients of the lane's Doppler deviation: |(j delta)^q / q!|
+                           // with the sign of j^q's nonzero part
     int dlo, Hs, NB, TB;   // lowest lag read, lag stride of s_G (even), blocks per round / per LDS tile
     int my_b, my_l, off;   // this thread's (block, lag pair) item; this lane's lag offset
+    int seg_lo, seg_hi;    // sample range of the step this workgroup sums (the whole step
+                           // unless the step is split into segments)
 };
 
 // One (tile, step): stage samples, then per round of NB blocks form the lag moments
@@ -129,8 +131,8 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
     const int tid = threadIdx.x;
     const double centre = 0.5 * (double)(a.L - 1);
     const int Hs = st.Hs;
-    for (int s0 = 0; s0 < a.L; s0 += st.TB * kFB) {
-        const int tl = min(st.TB * kFB, a.L - s0);
+    for (int s0 = st.seg_lo; s0 < st.seg_hi; s0 += st.TB * kFB) {
+        const int tl = min(st.TB * kFB, st.seg_hi - s0);
         const int nblk = (tl + kFB - 1) / kFB;
         __syncthreads();
         {
@@ -192,19 +194,17 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                         }
                     }
                 }
-                // s = m0 + j c1 m1 + c2 m2 + j c3 m3
+                // s = sum_q (j delta)^q / q! m_q: even q real, odd q imaginary
                 float sr = m[0][0], si = m[0][1];
-                if constexpr (Q > 1) {
-                    sr = fmaf(-st.c1, m[1][1], sr);
-                    si = fmaf(st.c1, m[1][0], si);
-                }
-                if constexpr (Q > 2) {
-                    sr = fmaf(st.c2, m[2][0], sr);
-                    si = fmaf(st.c2, m[2][1], si);
-                }
-                if constexpr (Q > 3) {
-                    sr = fmaf(-st.c3, m[3][1], sr);
-                    si = fmaf(st.c3, m[3][0], si);
+#pragma unroll
+                for (int q = 1; q < Q; ++q) {
+                    if (q & 1) {
+                        sr = fmaf(-st.c[q], m[q][1], sr);
+                        si = fmaf(st.c[q], m[q][0], si);
+                    } else {
+                        sr = fmaf(st.c[q], m[q][0], sr);
+                        si = fmaf(st.c[q], m[q][1], si);
+                    }
                 }
                 cr = fmaf(W.x, sr, fmaf(-W.y, si, cr));
                 ci = fmaf(W.x, si, fmaf(W.y, sr, ci));
@@ -217,19 +217,22 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
     }
 }
 
-template <int kMode>   // GEOLOC_DELAY_LINEAR, _ROUND or _SINC
+template <int kMode, int kQMax>   // GEOLOC_DELAY_LINEAR, _ROUND or _SINC; most Taylor terms
 __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     __shared__ float2 s_y[kFT + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
-    __shared__ __align__(16) float2 s_G[kFQ * 512];   // [round block][q][lag], <= 512 (block, lag) slots
+    __shared__ __align__(16) float2 s_G[kQMax * 512];   // [round block][q][lag], <= 512 (block, lag) slots
     __shared__ float2 s_rot[kFB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
 
     const int tid = threadIdx.x;
-    // workgroup -> (point tile, group of (pair, step) items), as in the per-point kernel
+    // workgroup -> (point tile, group of (pair, step) items, segment of the step)
     const int64_t tile = blockIdx.x % a.n_tiles;
-    const int group = (int)(blockIdx.x / a.n_tiles);
+    const int gs = (int)(blockIdx.x / a.n_tiles);
+    const int group = gs % a.n_groups;
+    const int seg = gs / a.n_groups;
+    const bool segmented = a.n_segs > 1;
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
     const int64_t it_hi = n_items * (group + 1) / a.n_groups;
@@ -264,7 +267,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         float tlo = valid ? th : FLT_MAX, thi = valid ? th : -FLT_MAX;
         wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
         if (dhi < dlo) {                               // no grid cell in this tile: nothing to add
-            if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = 0;
+            if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = 0;
+            if (segmented && valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(0.f, 0.f);
             continue;
         }
         const int64_t spread = (int64_t)dhi - (int64_t)dlo;
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         int Q = 0;
         if (xr == xr && xr < 1.f) {
             float term = 1.f;
-            for (int q = 1; q <= kFQ; ++q) {
+            for (int q = 1; q <= kQMax; ++q) {
                 term *= xr / q;
                 if (term <= kFTol) {
                     Q = q;
@@ -286,8 +290,11 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         constexpr int kTaps = kMode == GEOLOC_DELAY_SINC ? kSincTaps : 2;
         constexpr int kTapLo = kMode == GEOLOC_DELAY_SINC ? kSincLo : 0;
         const bool fact = Q > 0 && spread + kTaps <= kFH;
-        if (tid == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
-        if (!fact) continue;                           // uniform: the per-point kernel takes it
+        if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
+        if (!fact) {                                   // uniform: the per-point kernel takes it
+            if (segmented && valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(0.f, 0.f);
+            continue;
+        }
 
         FactStep st;
         const int H = (int)spread + kTaps;
@@ -299,9 +306,15 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(alpha, st.w);
         // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
         const float dl = (float)(two_pi * cyc - (double)tbar);
-        st.c1 = dl;
-        st.c2 = -0.5f * dl * dl;
-        st.c3 = -dl * dl * dl * (1.f / 6.f);
+        {
+            // (j dl)^q / q! = j^q dl^q / q!: j^q is 1, j, -1, -j in turn
+            float t = 1.f;
+#pragma unroll
+            for (int q = 0; q < kFQWide; ++q) {
+                st.c[q] = ((q & 2) ? -t : t);
+                t *= dl / (float)(q + 1);
+            }
+        }
         st.dlo = dlo - kTapLo;
         st.Hs = 2 * Hg;
         st.NB = min(kFTB, 256 / Hg);
@@ -309,6 +322,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         st.my_b = tid / Hg;
         st.my_l = 2 * (tid - st.my_b * Hg);
         st.off = valid ? d0 - dlo : 0;
+        st.seg_lo = segmented ? seg * a.seg_len : 0;
+        st.seg_hi = segmented ? min(a.L, (seg + 1) * a.seg_len) : a.L;
         if (tid < kFB) {
             float sn, cs;
             sincosf(tbar * ((float)tid - 0.5f * (float)(kFB - 1)), &sn, &cs);
@@ -318,27 +333,70 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         switch (Q) {
             case 1: fact_step<kMode, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
             case 2: fact_step<kMode, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 3: fact_step<kMode, (kFQ < 3 ? kFQ : 3)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            default: fact_step<kMode, kFQ>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kMode, 3>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 4: fact_step<kMode, 4>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kMode, kQMax>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+        }
+        if (segmented) {
+            if (valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(cr, ci);
+            continue;
         }
         const double pw = (double)cr * cr + (double)ci * ci;
         jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
     }
-    if (!valid) return;
+    if (!valid || segmented) return;
     if (a.n_groups == 1)
         a.J[p] = (float)jacc;
     else
         a.partial[(int64_t)group * a.P + p] = jacc;
 }
 
-hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
-    dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
+// J[p] = (J[p] if loading) + sum over items of |sum over segments of cpart|^2 (or |.|), in a
+// fixed order.
+__global__ __launch_bounds__(256) void k_direct_seg_reduce(const float2* __restrict__ cpart, int32_t n_segs,
+                                                           int64_t n_items, int64_t P, int32_t load_J,
+                                                           int32_t accum_mode, float* __restrict__ J) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    double acc = load_J ? (double)J[p] : 0.0;
+    for (int64_t it = 0; it < n_items; ++it) {
+        double cr = 0.0, ci = 0.0;
+        for (int sg = 0; sg < n_segs; ++sg) {
+            const float2 v = cpart[((int64_t)sg * n_items + it) * P + p];
+            cr += v.x;
+            ci += v.y;
+        }
+        const double pw = cr * cr + ci * ci;
+        acc += (accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
+    }
+    J[p] = (float)acc;
+}
+
+hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
+    if (a.n_segs <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_direct_seg_reduce, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s,
+                       (const float2*)a.cpart, a.n_segs, (int64_t)a.n_pairs * a.kc, a.P, a.load_J, a.accum_mode, a.J);
+    return hipGetLastError();
+}
+
+template <int kQMax>
+static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
+    dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_ROUND>, grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax>), grid, block, 0, s, a, deferred);
     else if (delay_mode == GEOLOC_DELAY_SINC)
-        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_SINC>, grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax>), grid, block, 0, s, a, deferred);
     else
-        hipLaunchKernelGGL(k_direct_fact<GEOLOC_DELAY_LINEAR>, grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax>), grid, block, 0, s, a, deferred);
+}
+
+hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
+                              hipStream_t s) {
+    if (wide_doppler)
+        launch_fact_q<kFQWide>(a, deferred, delay_mode, s);
+    else
+        launch_fact_q<kFQ>(a, deferred, delay_mode, s);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgeoloc.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
@@ -68,7 +68,7 @@ class geoloc_plan_info(ctypes.Structure):
         ("geometry_ms", ctypes.c_double), ("correlate_ms", ctypes.c_double), ("interp_ms", ctypes.c_double),
         ("map_ms", ctypes.c_double),
         ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32), ("tile_shear", ctypes.c_int32),
-        ("tile_transpose", ctypes.c_int32),
+        ("tile_transpose", ctypes.c_int32), ("step_segments", ctypes.c_int32), ("segment_len", ctypes.c_int32),
     ]
 
 

@@ -269,3 +269,23 @@ def test_sinc_delay_wide_tiles_and_point_list(torch, G):
                 lat=la[sel], lon=lo[sel], grid_kind=G.GRID_POINTS, delay_mode=G.DELAY_SINC) as plan:
         Jg = plan.map(caps, scn.states).cpu().numpy()
     assert err_J(Jg, Jo) <= DIRECT_TOL
+
+
+@pytest.mark.parametrize("delay,accum,spacing", [(0, 0, 500.0), (2, 1, 500.0), (1, 0, 500.0), (0, 0, 8000.0)])
+def test_step_segments(torch, G, delay, accum, spacing):
+    """A small grid with long steps: the factored kernel splits each 41,000-sample step into
+    coherent segments (the last one 40 samples long) and adds their complex partial sums
+    before |C|^2 (or |C|). On 8 km cells part of the tile-steps also go to the per-point pass
+    after the segment reduction."""
+    wl = configs.MAP_1E6.with_(n_rows=30, n_cols=41, spacing_m=spacing, n_samples=123_000, step_len=41_000)
+    scn = sim.make_scenario(wl, 40 + delay)
+    log(f"step segments delay={delay} accum={accum} spacing={spacing}")
+    Jo = oracle.map_scenario(scn, delay_mode=delay, accum_mode=accum)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn, delay_mode=delay, accum_mode=accum) as plan:
+        Jg = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        info = plan.info()
+    log(f"  {info['step_segments']} segments of {info['segment_len']}, err_J = {err_J(Jg, Jo):.3g}")
+    assert info["step_segments"] == 11 and info["segment_len"] == 4096
+    assert err_J(Jg, Jo) <= DIRECT_TOL
+    check_argmax(Jg, Jo, DIRECT_TOL)
