@@ -62,19 +62,20 @@ def measured_traffic():
 
 def tile_index(rows: int, cols: int, w: int, h: int, shear: int, transpose: int):
     """Flat point index of every (tile, lane) of a RECT tiling, -1 outside the grid: tiles
-    of h rows of w cells, row i shifted by shear * i columns (rows and columns swapped with
-    transpose), in bands of h rows."""
+    of h rows of w cells, row i starting floor(shear * i / 256) columns further along (rows
+    and columns swapped with transpose), in bands of h rows."""
     import numpy as np
     R, C = (cols, rows) if transpose else (rows, cols)
     ty_n = -(-R // h)
-    tx_n = -(-(C + abs(shear) * (h - 1)) // w)
+    span = ((abs(shear) * (h - 1)) >> 8) + 1 if shear else 0
+    tx_n = -(-(C + span) // w)
     tile = np.arange(ty_n * tx_n, dtype=np.int64)[:, None]
-    lane = np.arange(256, dtype=np.int64)[None, :]
+    lane = np.arange(w * h, dtype=np.int64)[None, :]
     ty, tx = np.divmod(tile, tx_n)
     r0 = ty * h
     r = r0 + lane // w
-    b0 = -shear * (r0 + h - 1) if shear > 0 else -shear * r0
-    c = shear * r + b0 + tx * w + lane % w
+    b0 = -((shear * np.where(shear > 0, r0 + h - 1, r0)) >> 8)
+    c = ((shear * r) >> 8) + b0 + tx * w + lane % w
     valid = (r < R) & (c >= 0) & (c < C)
     rr, cc = (c, r) if transpose else (r, c)
     return np.where(valid, rr * cols + cc, -1)
@@ -86,9 +87,10 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     as the kernel does (lag spread H = max d0 - min d0 + 2, Taylor order Q from the tile's
     Doppler spread, deferred when H > 128 or no Q <= 4 bounds the remainder). Per factored
     tile and step: rotation of the reference samples 6 L; lag moments H L (6 + 2 + 4 (Q - 1));
-    per point and 64-sample block 6 Q for the two-tap interpolation of the moments (LINEAR
-    only), 4 (Q - 1) for the Taylor coefficients, 8 + 6 for the block weight and its
-    recurrence. Returns (flops, factored units, deferred tile-steps, all tile-steps)."""
+    per point and 64-sample block 4 flops per Taylor term and lag read (two lags for LINEAR,
+    whose interpolation weights are folded into the Taylor coefficients; one for ROUND) and
+    6 for the block weight (one Horner step, a complex product by a unit phasor). Returns
+    (flops, factored units, deferred tile-steps, all tile-steps)."""
     import numpy as np
     info = plan.info()
     idx = torch.from_numpy(tile_index(wl.n_rows, wl.n_cols, info["tile_cols"], info["tile_rows"],
@@ -125,7 +127,7 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         ok = (terms <= FTOL) & (xr < 1).unsqueeze(-1)
         Q = torch.where(ok.any(-1), ok.float().argmax(-1) + 1, torch.zeros_like(xr, dtype=torch.int64)).double()
         fac = (Q > 0) & (H <= FH) & (nval > 0)     # tiles with no grid cell do no work
-        per_point = nblk * ((0 if delay_round else 6 * Q) + 4 * (Q - 1) + 14)
+        per_point = nblk * ((4 if delay_round else 8) * Q + 6)
         f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
         flops += float(torch.where(fac, f, torch.zeros_like(f)).sum())
         units += float(torch.where(fac, nval * L, torch.zeros_like(f)).sum())
@@ -444,7 +446,7 @@ def main() -> int:
                 "kernel": "k_direct_fact", "launch_ms": round(k_ms, 4), "units_per_launch": units_per_launch,
                 "flop_per_launch": flops_per_launch, "flop_per_unit": round(f_map / max(f_units, 1.0), 4),
                 "deferred_tile_steps": f"{n_def}/{n_ts}",
-                "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear']}"
+                "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f} columns/row"
                         f"{' transposed' if info['tile_transpose'] else ''}",
                 "pointwise_equivalent_tflops": round(FLOP_PER_UNIT_POINTWISE * units_per_launch / (k_ms / 1e3) / 1e12,
                                                      3)}

@@ -140,8 +140,8 @@ typedef struct geoloc_plan_info {
                                   method, of the per-point pass over (tile, step) pairs the
                                   factored kernel left to it                              */
     double map_ms;             /* ... of whole geoloc_map calls, first to last kernel    */
-    int32_t tile_rows, tile_cols;   /* workgroup tile of the last map: rows x cells per row */
-    int32_t tile_shear;        /* column shift per tile row (diagonal tiles)              */
+    int32_t tile_rows, tile_cols;   /* tile of the last map: rows x cells per row (256 or 512 cells) */
+    int32_t tile_shear;        /* column shift per tile row, in 1/256 columns (slanted tiles) */
     int32_t tile_transpose;    /* 1: rows and columns swap roles in the tile              */
     int32_t step_segments;     /* direct method: coherent segments each step is split into
                                   across workgroups (1 = not split); their complex partial

@@ -38,6 +38,7 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr uint32_t kMagic = 0x67656f6cu;  // "geol"
 constexpr int64_t kGeomChunkBytes = 512ll << 20;
+constexpr int32_t kMaxShear = 4 * kShearOne;   // steepest tile shear: 4 columns per row
 
 struct TimedSpan {
     int kind;  // 0 geometry, 1 correlate, 2 interp, 3 whole map
@@ -58,6 +59,7 @@ struct geoloc_plan_s {
     PointTiling base_tiling{};       // 16 x 16 squares (RECT) or runs of 256 points (POINTS)
     std::vector<PointTiling> tile_shapes;   // RECT: candidate tilings of the factored kernel
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
+    int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate
     std::vector<double> h_lat, h_lon;       // grid coordinates (host copy, for the tile choice)
     int32_t kc = 1;  // steps per geometry chunk
     // device scratch
@@ -251,11 +253,15 @@ void host_delay_doppler(const geoloc_plan_s* p, double lat, double lon, const do
 }
 
 // Tile shape for the factored kernel: from the delay and Doppler gradients at the grid
-// centre (middle step) of every pair, the candidate with the least predicted VALU work per
-// correlation summed over the pairs, counting the lanes its tiles leave outside the grid.
-// The lag moments cost about (8 + 4Q) / NB instructions per correlation (NB blocks per
-// round, from the lag spread H) and the per-point combination (6Q + 8) / 64; a tile that
-// the factored kernel would defer costs about 13. Taylor orders 5 and 6 need the kernel's
+// centre (middle step) of every pair, the candidate (shape of 256 or 512 cells, shear of
+// whole columns per row or along a pair's lines of equal delay) with the least predicted
+// VALU work per correlation summed over the pairs, counting the lanes its tiles leave
+// outside the grid. The lag moments cost about (8 + 4Q) instructions per lag pair and
+// sample, shared by the tile's cells (waves without a (block, lag pair) item skip them),
+// and the per-point combination about (4Q + 6) / 64 (LINEAR; fewer for ROUND, more for
+// SINC); a tile that the factored kernel would defer costs about 13. A tiling whose launch
+// has fewer than 768 workgroups (three per CU) is charged for the idle share of the chip,
+// and SINC, bound by its per-point work and registers, keeps to 256-cell tiles. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
 // are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
 void choose_tiling(geoloc_plan_t p, const double* states) {
@@ -263,39 +269,86 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     p->fact_wide = false;
     if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 || p->tile_shapes.empty()) return;
     const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
-    const int64_t ra = std::max<int64_t>(r0 - 1, 0), rb = std::min<int64_t>(r0 + 1, p->rows - 1);
-    const int64_t ca = std::max<int64_t>(c0 - 1, 0), cb = std::min<int64_t>(c0 + 1, p->cols - 1);
-    // gradients [pair][delay, doppler][d/drow, d/dcol]
-    std::vector<std::array<double, 4>> grads;
+    const bool has_r = p->rows >= 3, has_c = p->cols >= 3;
+    // per pair, a quadratic model of the delay D (samples) and the Doppler th (radians per
+    // sample) about the grid centre, in cells: [D_r, D_c, th_r, th_c, D_rr, D_cc, D_rc,
+    // th_rr, th_cc, th_rc] from the 3 x 3 stencil of neighbouring cells
+    std::vector<std::array<double, 10>> grads;
+    std::vector<double> weight;
     for (const int2 pr : p->pairs) {
         const double* si = states + ((size_t)k * p->n_rx + pr.x) * 6;
         const double* sj = states + ((size_t)k * p->n_rx + pr.y) * 6;
-        std::array<double, 4> g{0, 0, 0, 0};
-        double D1, t1, D2, t2;
-        if (rb > ra) {
-            host_delay_doppler(p, p->h_lat[ra], p->h_lon[c0], si, sj, &D1, &t1);
-            host_delay_doppler(p, p->h_lat[rb], p->h_lon[c0], si, sj, &D2, &t2);
-            g[0] = (D2 - D1) / (double)(rb - ra);
-            g[2] = (t2 - t1) / (double)(rb - ra);
+        double D[3][3], T[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const int64_t r = has_r ? r0 + i - 1 : r0, c = has_c ? c0 + j - 1 : c0;
+                host_delay_doppler(p, p->h_lat[r], p->h_lon[c], si, sj, &D[i][j], &T[i][j]);
+            }
+        std::array<double, 10> g{};
+        if (has_r) {
+            g[0] = 0.5 * (D[2][1] - D[0][1]);
+            g[2] = 0.5 * (T[2][1] - T[0][1]);
+            g[4] = D[2][1] + D[0][1] - 2.0 * D[1][1];
+            g[7] = T[2][1] + T[0][1] - 2.0 * T[1][1];
         }
-        if (cb > ca) {
-            host_delay_doppler(p, p->h_lat[r0], p->h_lon[ca], si, sj, &D1, &t1);
-            host_delay_doppler(p, p->h_lat[r0], p->h_lon[cb], si, sj, &D2, &t2);
-            g[1] = (D2 - D1) / (double)(cb - ca);
-            g[3] = (t2 - t1) / (double)(cb - ca);
+        if (has_c) {
+            g[1] = 0.5 * (D[1][2] - D[1][0]);
+            g[3] = 0.5 * (T[1][2] - T[1][0]);
+            g[5] = D[1][2] + D[1][0] - 2.0 * D[1][1];
+            g[8] = T[1][2] + T[1][0] - 2.0 * T[1][1];
         }
-        if (!std::isfinite(g[0] + g[1] + g[2] + g[3])) return;
-        grads.push_back(g);
+        if (has_r && has_c) {
+            g[6] = 0.25 * (D[2][2] - D[2][0] - D[0][2] + D[0][0]);
+            g[9] = 0.25 * (T[2][2] - T[2][0] - T[0][2] + T[0][0]);
+        }
+        double sum = 0.0;
+        for (double v : g) sum += v;
+        if (!std::isfinite(sum)) return;
+        // pairs of the same geometry (stacked sub-bands of one capture) count once, weighted
+        bool seen = false;
+        for (size_t i = 0; i < grads.size() && !seen; ++i)
+            if (grads[i] == g) {
+                weight[i] += 1.0;
+                seen = true;
+            }
+        if (!seen) {
+            grads.push_back(g);
+            weight.push_back(1.0);
+        }
     }
+    // workgroups of a launch with this tiling: too few to fill the chip cost their idle share
+    const double groups = (double)p->n_groups * (p->n_segs > 1 ? p->n_segs : 1);
+    auto fill = [&](const PointTiling& t) {
+        return std::max(1.0, 768.0 / ((double)(t.tiles_x * t.tiles_y) * groups));
+    };
+    // per-point instructions per block: Taylor terms times lags read, plus one Horner step
+    auto combine = [&](int Q) {
+        return p->delay_mode == GEOLOC_DELAY_SINC ? 18.0 * Q + 6.0
+                                                  : (p->delay_mode == GEOLOC_DELAY_ROUND ? 2.0 : 4.0) * Q + 6.0;
+    };
     auto cost = [&](const PointTiling& t, int* q_need) {
         double total = 0.0;
         *q_need = 0;
-        for (const auto& g : grads) {
-            const double gr = t.transpose ? g[1] : g[0], gc = t.transpose ? g[0] : g[1];
-            const double hr = t.transpose ? g[3] : g[2], hc = t.transpose ? g[2] : g[3];
-            const double H = std::fabs(gr + t.shear * gc) * (t.tile_h - 1) + std::fabs(gc) * (t.tile_w - 1) + 3.0;
-            const double xr =
-                0.5 * (std::fabs(hr + t.shear * hc) * (t.tile_h - 1) + std::fabs(hc) * (t.tile_w - 1)) * 32.0;
+        const double sh = (double)t.shear / kShearOne;
+        const double jag = (t.shear % kShearOne) ? 1.0 : 0.0;   // rounding of fractional row offsets
+        const int lanes = tile_lanes(t);
+        const double Rn = (double)(t.transpose ? p->cols : p->rows), Cn = (double)(t.transpose ? p->rows : p->cols);
+        const double hl = t.tile_h - 1.0, wl = t.tile_w - 1.0 + jag;
+        // spread over a tile of a quantity with gradient (fr, fc) and second derivatives
+        // (frr, fcc, frc): the linear part, the bend along the tile, and the drift of the
+        // slope between the grid centre and an average tile
+        auto spread = [&](double fr, double fc, double frr, double fcc, double frc) {
+            const double fuu = frr + 2.0 * sh * frc + sh * sh * fcc;
+            return std::fabs(fr + sh * fc) * hl + std::fabs(fc) * wl + 0.25 * std::fabs(fuu) * hl * hl +
+                   0.25 * std::fabs(fcc) * wl * wl +
+                   0.25 * (std::fabs(frr + sh * frc) * Rn + std::fabs(frc + sh * fcc) * Cn) * hl;
+        };
+        for (size_t gi = 0; gi < grads.size(); ++gi) {
+            const auto& g = grads[gi];
+            const bool tr = t.transpose != 0;
+            const double H = spread(tr ? g[1] : g[0], tr ? g[0] : g[1], tr ? g[5] : g[4], tr ? g[4] : g[5], g[6]) + 3.0;
+            const double xr = 0.5 * spread(tr ? g[3] : g[2], tr ? g[2] : g[3], tr ? g[8] : g[7], tr ? g[7] : g[8], g[9]) *
+                              (0.5 * 64.0);
             int Q = 0;
             double term = 1.0;
             for (int q = 1; q <= 6 && xr < 1.0; ++q) {
@@ -309,21 +362,40 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             if (Q > 0 && H <= 128.0) {
                 const int Hg = (int)std::ceil(H / 2.0);
                 const int NB = std::min(32, 256 / Hg);
-                c = ((8.0 + 4.0 * Q) / NB + (6.0 * Q + 8.0) / 64.0) * (Q > 4 ? 1.5 : 1.0);
+                const double waves = std::ceil(NB * Hg / 64.0);   // waves busy with moments
+                c = ((8.0 + 4.0 * Q) * waves * 64.0 / (NB * lanes) + combine(Q) / 64.0) * (Q > 4 ? 1.5 : 1.0);
                 *q_need = std::max(*q_need, Q);
             }
-            total += c;
+            total += weight[gi] * c;
         }
-        return total * (double)(t.tiles_x * t.tiles_y * kTilePoints) / (double)p->P;
+        return total * (double)(t.tiles_x * t.tiles_y * lanes) / (double)p->P * fill(t);
     };
     int q_best = 0, q = 0;
     double best = cost(p->base_tiling, &q_best);
-    for (const auto& t : p->tile_shapes) {
-        const double c = cost(t, &q);
-        if (c < 0.97 * best) {
-            best = c;
-            q_best = q;
-            p->tiling = t;
+    for (const auto& shape : p->tile_shapes) {
+        // the SINC combination is bound by per-point work and registers: 256-cell tiles only
+        if (p->delay_mode == GEOLOC_DELAY_SINC && tile_lanes(shape) != kTilePoints) continue;
+        // shears: whole columns per row, and the slope of each pair's lines of equal delay
+        std::vector<int32_t> shears = {-2 * kShearOne, -kShearOne, 0, kShearOne, 2 * kShearOne};
+        for (const auto& g : grads) {
+            const double gr = shape.transpose ? g[1] : g[0], gc = shape.transpose ? g[0] : g[1];
+            if (std::fabs(gc) > 1e-12) {
+                const double sg = std::max(-4.0, std::min(4.0, -gr / gc));
+                shears.push_back((int32_t)std::lround(sg * kShearOne));
+            }
+        }
+        std::sort(shears.begin(), shears.end());
+        shears.erase(std::unique(shears.begin(), shears.end()), shears.end());
+        for (const int32_t sh : shears) {
+            PointTiling t = shape;
+            t.shear = std::max(-kMaxShear, std::min(kMaxShear, sh));
+            tiling_counts(t);
+            const double c = cost(t, &q);
+            if (c < 0.97 * best) {
+                best = c;
+                q_best = q;
+                p->tiling = t;
+            }
         }
     }
     p->fact_wide = q_best > 4;
@@ -706,26 +778,29 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         p->base_tiling = p->tiling = t;
         p->max_tiles = t.tiles_x * t.tiles_y;
         if (d->grid_kind == GEOLOC_GRID_RECT) {
-            // square, tall and taller tiles, sheared by -2..2 columns per row, either way round
-            const int shapes[3][2] = {{16, 16}, {8, 32}, {4, 64}};
+            // tile shapes of 256 and 512 cells, either way round; the map picks one and its
+            // shear from the geometry, with |shear| <= kMaxShear (scratch is sized for that)
+            const int shapes[6][2] = {{16, 16}, {8, 32}, {4, 64}, {16, 32}, {8, 64}, {4, 128}};
             for (int tr = 0; tr < 2; ++tr)
-                for (int sh = -2; sh <= 2; ++sh)
-                    for (const auto& wh : shapes) {
-                        PointTiling c = t;
-                        c.tile_w = wh[0];
-                        c.tile_h = wh[1];
-                        c.shear = sh;
-                        c.transpose = tr;
+                for (const auto& wh : shapes) {
+                    PointTiling c = t;
+                    c.tile_w = wh[0];
+                    c.tile_h = wh[1];
+                    c.transpose = tr;
+                    p->tile_shapes.push_back(c);
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        c.shear = sg * kMaxShear;
                         tiling_counts(c);
-                        p->tile_shapes.push_back(c);
                         p->max_tiles = std::max(p->max_tiles, c.tiles_x * c.tiles_y);
+                        p->max_table = std::max(p->max_table, c.tiles_x * c.tiles_y * tile_lanes(c));
                     }
+                }
         }
         p->h_lat.assign(d->lat, d->lat + (d->grid_kind == GEOLOC_GRID_RECT ? d->n_rows : P));
         p->h_lon.assign(d->lon, d->lon + (d->grid_kind == GEOLOC_GRID_RECT ? d->n_cols : P));
     }
 
-    const int64_t table_points = p->max_tiles * kTilePoints;  // tile-major >= P
+    const int64_t table_points = std::max(p->max_table, p->base_tiling.tiles_x * p->base_tiling.tiles_y * kTilePoints);
     const int64_t per_step = (int64_t)p->n_pairs * table_points * 16;
     int64_t kc = kGeomChunkBytes / per_step;
     if (kc < 1) kc = 1;

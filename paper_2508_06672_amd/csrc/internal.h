@@ -13,31 +13,41 @@ namespace geoloc {
 
 constexpr double kLightSpeed = 299792458.0;
 
-// Points handled by one workgroup of the correlation kernels: a tile of 256 cells of a
-// RECT grid (neighbouring cells have neighbouring delays, so the lag spread a tile needs
-// in LDS stays small), or 256 consecutive entries of a POINTS list.
+// Points handled by one workgroup of the correlation kernels: a tile of 256 (or, for the
+// factored kernel, 512) cells of a RECT grid (neighbouring cells have neighbouring delays,
+// so the lag spread a tile needs in LDS stays small), or 256 consecutive entries of a
+// POINTS list.
 //
-// A RECT tile is tile_h rows of tile_w cells in which row i is shifted by shear * i
-// columns, a parallelogram that can follow a diagonal line of equal delay (with
-// `transpose`, rows and columns swap roles). Tiles stack in bands of tile_h rows; each band
-// holds tiles_x tiles, enough to cover the sheared band, and cells outside the grid are
-// invalid lanes. shear = 0, 16 x 16 is the plain square tiling.
-constexpr int kTilePoints = 256;
+// A RECT tile is tile_h rows of tile_w cells in which row i starts floor(shear * i / 256)
+// columns further along, a parallelogram that can follow a line of equal delay at any
+// slope (with `transpose`, rows and columns swap roles). Tiles stack in bands of tile_h
+// rows; each band holds tiles_x tiles, enough to cover the sheared band, and cells outside
+// the grid are invalid lanes. shear = 0, 16 x 16 is the plain square tiling.
+constexpr int kTilePoints = 256;       // cells of the square tiling and of POINTS tiles
+constexpr int kMaxTileLanes = 512;     // most cells of any tile
+constexpr int kShearOne = 256;         // shear unit: one column per row
 
 struct PointTiling {
     int64_t rows, cols;     // RECT: grid shape; POINTS: 1 x P
     int32_t tile_w, tile_h; // cells per tile row, rows per tile (POINTS: 256 x 1)
     int64_t tiles_x, tiles_y;   // tiles per band, bands
-    int32_t shear;          // column shift per tile row (RECT)
+    int32_t shear;          // column shift per tile row in 1/256 columns (RECT)
     int32_t transpose;      // 1: the roles of rows and columns are swapped (RECT)
 };
 
-// Tile count of a tiling with the given shape over a rows x cols grid.
+__host__ __device__ inline int tile_lanes(const PointTiling& t) { return t.tile_w * t.tile_h; }
+
+// Column offset of row r: floor(shear * r / 256) (an arithmetic shift rounds down).
+__host__ __device__ inline int64_t shear_offset(int32_t shear, int64_t r) { return ((int64_t)shear * r) >> 8; }
+
+// Tile count of a tiling with the given shape over a rows x cols grid. Within a band the row
+// offsets span at most floor(|shear| (tile_h - 1) / 256) + 1 columns.
 __host__ __device__ inline void tiling_counts(PointTiling& t) {
     const int64_t R = t.transpose ? t.cols : t.rows, C = t.transpose ? t.rows : t.cols;
-    const int64_t sh = t.shear < 0 ? -t.shear : t.shear;
+    const int64_t sh = t.shear < 0 ? -(int64_t)t.shear : (int64_t)t.shear;
+    const int64_t span = sh ? ((sh * (t.tile_h - 1)) >> 8) + 1 : 0;
     t.tiles_y = (R + t.tile_h - 1) / t.tile_h;
-    t.tiles_x = (C + sh * (t.tile_h - 1) + t.tile_w - 1) / t.tile_w;
+    t.tiles_x = (C + span + t.tile_w - 1) / t.tile_w;
 }
 
 __host__ __device__ inline int64_t tile_point(const PointTiling& t, int64_t tile, int lane, bool* valid) {
@@ -45,9 +55,9 @@ __host__ __device__ inline int64_t tile_point(const PointTiling& t, int64_t tile
     const int64_t R = t.transpose ? t.cols : t.rows, C = t.transpose ? t.rows : t.cols;
     const int64_t r0 = ty * t.tile_h;
     const int64_t r = r0 + lane / t.tile_w;
-    // first column of the band's sheared coordinate: the band's rows cover [0, C)
-    const int64_t b0 = t.shear > 0 ? -(int64_t)t.shear * (r0 + t.tile_h - 1) : -(int64_t)t.shear * r0;
-    const int64_t c = (int64_t)t.shear * r + b0 + tx * t.tile_w + lane % t.tile_w;
+    // the band's largest row offset maps to column 0, so its rows cover [0, C)
+    const int64_t b0 = -shear_offset(t.shear, t.shear > 0 ? r0 + t.tile_h - 1 : r0);
+    const int64_t c = shear_offset(t.shear, r) + b0 + tx * t.tile_w + lane % t.tile_w;
     *valid = (r < R) && (c >= 0) && (c < C);
     const int64_t rr = t.transpose ? c : r, cc = t.transpose ? r : c;
     return *valid ? rr * t.cols + cc : 0;
@@ -60,7 +70,7 @@ struct DirectArgs {
     const int2* pairs;       // [n_pairs]
     float* J;                // [P]
     PointTiling tiling;
-    int64_t n_tiles;         // tiles_x * tiles_y; D / nu are [n_pairs][kc][n_tiles][256]
+    int64_t n_tiles;         // tiles_x * tiles_y; D / nu are [n_pairs][kc][n_tiles][tile lanes]
     int64_t N, P;
     int32_t L, k0, kc, n_pairs;
     double inv_fs;

@@ -133,13 +133,17 @@ void k_direct(DirectArgs a) {
     // workgroup -> (point tile, group): with n_groups > 1 each group sums its share of the
     // chunk's (pair, step) items, pair-major, into its own partial row, reduced afterwards
     // in a fixed order
-    const int64_t tile = blockIdx.x % a.n_tiles;
-    const int group = (int)(blockIdx.x / a.n_tiles);
+    // (a tile of 512 cells is two workgroups, one per half)
+    const int halves = tile_lanes(a.tiling) / 256;
+    const int64_t sub = blockIdx.x % (a.n_tiles * halves);
+    const int64_t tile = sub / halves;
+    const int lane = (int)(sub - tile * halves) * 256 + tid;
+    const int group = (int)(blockIdx.x / (a.n_tiles * halves));
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
     const int64_t it_hi = n_items * (group + 1) / a.n_groups;
     bool valid;
-    const int64_t p = tile_point(a.tiling, tile, tid, &valid);
+    const int64_t p = tile_point(a.tiling, tile, lane, &valid);
     // item groups: a masked pass adds onto the partial sums the factored kernel wrote
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
@@ -156,7 +160,7 @@ void k_direct(DirectArgs a) {
             // with a mask, only the (tile, step) pairs the factored kernel left over
             if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
+            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * (halves * 256) + lane;
             double D = valid ? a.D[gi] : 0.0;
             const double nu = valid ? a.nu[gi] : 0.0;
             // keep the integer lag representable whatever the geometry (NaN included);
@@ -245,7 +249,7 @@ int32_t direct_groups(int64_t n_tiles, int64_t n_items) {
 }
 
 hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s) {
-    dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
+    dim3 grid((unsigned)(a.n_tiles * (tile_lanes(a.tiling) / 256) * a.n_groups)), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
         hipLaunchKernelGGL(k_direct<true>, grid, block, 0, s, a);
     else

@@ -46,7 +46,8 @@ constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
 constexpr int kFVS = kFB + 2;    // LDS stride of the reference samples of one block
 constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
 
-// Workgroup min / max of two ints and two floats (wave shuffles, then LDS).
+// Workgroup min / max of two ints and two floats (wave shuffles, then LDS; the barrier
+// before the LDS writes keeps them clear of the previous call's reads).
 __device__ inline void wg_extent(int& dlo, int& dhi, float& tlo, float& thi, int (*si)[4], float (*sf)[4]) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -110,27 +111,55 @@ __device__ inline void block_moments2(const float2* __restrict__ v, const float2
 // Values of one (tile, step) that both phases use.
 struct FactStep {
     int64_t n_step;        // first sample of the step
-    double cyc;            // this lane's FDOA in cycles per sample
-    float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
-    float alpha;           // this lane's fractional lag
-    float w[kSincTaps];    // this lane's windowed-sinc weights (SINC only)
-    float c[kFQWide];      // Taylor coefficients of the lane's Doppler deviation: |(j delta)^q / q!|
-                           // with the sign of j^q's nonzero part
     int dlo, Hs, NB, TB;   // lowest lag read, lag stride of s_G (even), blocks per round / per LDS tile
-    int my_b, my_l, off;   // this thread's (block, lag pair) item; this lane's lag offset
+    int my_b, my_l;        // this thread's (block, lag pair) item
     int seg_lo, seg_hi;    // sample range of the step this workgroup sums (the whole step
                            // unless the step is split into segments)
 };
 
+// Per-point values of one (tile, step).
+struct FactPoint {
+    double cyc;            // FDOA in cycles per sample
+    float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
+    float alpha;           // fractional lag
+    float w[kSincTaps];    // windowed-sinc weights (SINC only)
+    float c[kFQWide];      // Taylor coefficients of the Doppler deviation: |(j delta)^q / q!|
+                           // with the sign of j^q's nonzero part
+    int off;               // lag offset of the first lag read in s_G
+};
+
 // One (tile, step): stage samples, then per round of NB blocks form the lag moments
-// (phase 1) and combine them per point (phase 2). Adds the step's C into (cr, ci).
-template <int kMode, int Q>
+// (phase 1) and combine them per point (phase 2). Adds each of the thread's kPPT points'
+// share of C into (cr[k], ci[k]).
+//
+// The moments of a round sit lag-major, s_G[(block * Hs + lag) * Q + q], so that a point
+// reads the 2Q (LINEAR) or 8Q (SINC) values of its lags from one base address. Per block a
+// point forms s_b = sum_q a_q m_q and folds it into acc = acc conj(E) + s_b (E = e^{j theta_p
+// B}, Horner's rule for sum_b E^b s_b); at the end of an LDS tile acc times the exact FP64
+// weight of the tile's last block goes into C. For LINEAR the interpolation weights are
+// folded into the Taylor coefficients once per step: a_q m_q = ((1 - a) a_q) G_q(d0) +
+// (a a_q) G_q(d0 + 1), four FMAs per Taylor term and block.
+template <int kMode, int Q, int kPPT>
 __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
-                          const FactStep& st, float2* s_y, float2* s_v, float2* s_G, const float2* s_rot, float& cr,
-                          float& ci) {
+                          const FactStep& st, const FactPoint (&pt)[kPPT], float2* s_y, float2* s_v, float2* s_G,
+                          const float2* s_rot, float (&cr)[kPPT], float (&ci)[kPPT]) {
     const int tid = threadIdx.x;
     const double centre = 0.5 * (double)(a.L - 1);
     const int Hs = st.Hs;
+    // per-point coefficients of the lags the point reads (see above)
+    constexpr int kT = kMode == GEOLOC_DELAY_LINEAR ? 2 : 1;
+    float cf[kPPT][kT][Q];
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if constexpr (kMode == GEOLOC_DELAY_LINEAR) {
+                cf[k][0][q] = (1.f - pt[k].alpha) * pt[k].c[q];
+                cf[k][1][q] = pt[k].alpha * pt[k].c[q];
+            } else {
+                cf[k][0][q] = pt[k].c[q];
+            }
+        }
     for (int s0 = st.seg_lo; s0 < st.seg_hi; s0 += st.TB * kFB) {
         const int tl = min(st.TB * kFB, st.seg_hi - s0);
         const int nblk = (tl + kFB - 1) / kFB;
@@ -153,78 +182,93 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
             }
         }
         __syncthreads();
-        float2 W = cis_cycles(st.cyc * ((double)s0 + 0.5 * (double)(kFB - 1) - centre));
+        float accr[kPPT], acci[kPPT];   // sum_b conj(E)^(last - b) s_b over this LDS tile
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) accr[k] = acci[k] = 0.f;
         for (int bb = 0; bb < nblk; bb += st.NB) {
             // phase 1: item (my_b, my_l) forms the moments of block bb + my_b at lags my_l, my_l + 1
             const int b = bb + st.my_b;
             if (st.my_b < st.NB && b < nblk) {
-                float2 G0[Q], G1[Q];
-                block_moments2<Q>(s_v + b * kFVS, s_y + b * kFB + st.my_l, G0, G1);
+                float2 G[2][Q];
+                block_moments2<Q>(s_v + b * kFVS, s_y + b * kFB + st.my_l, G[0], G[1]);
+                float4* dst = reinterpret_cast<float4*>(s_G + (st.my_b * Hs + st.my_l) * Q);
 #pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    *reinterpret_cast<float4*>(s_G + (st.my_b * Q + q) * Hs + st.my_l) =
-                        make_float4(G0[q].x, G0[q].y, G1[q].x, G1[q].y);
+                for (int i = 0; i < Q; ++i) {
+                    const float2 u = G[(2 * i) / Q][(2 * i) % Q], w = G[(2 * i + 1) / Q][(2 * i + 1) % Q];
+                    dst[i] = make_float4(u.x, u.y, w.x, w.y);
+                }
             }
             __syncthreads();
-            // phase 2: every point combines 2Q moments per block
-            const int nb = min(st.NB, nblk - bb);
+            // phase 2: every point folds its blocks of this round into acc
+            const int nb = __builtin_amdgcn_readfirstlane(min(st.NB, nblk - bb));
+            const float2* g[kPPT];
+#pragma unroll
+            for (int k = 0; k < kPPT; ++k) g[k] = s_G + pt[k].off * Q;
             for (int w = 0; w < nb; ++w) {
-                const float2* g = s_G + w * Q * Hs + st.off;
-                float m[Q][2];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    if constexpr (kMode == GEOLOC_DELAY_SINC) {
+                for (int k = 0; k < kPPT; ++k) {
+                    const float2 E = pt[k].ERB;
+                    float sr = fmaf(accr[k], E.x, acci[k] * E.y);    // acc * conj(E)
+                    float si = fmaf(acci[k], E.x, -(accr[k] * E.y));
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
                         float mr = 0.f, mi = 0.f;
+                        if constexpr (kMode == GEOLOC_DELAY_SINC) {
 #pragma unroll
-                        for (int t = 0; t < kSincTaps; ++t) {
-                            const float2 gt = g[q * Hs + t];
-                            mr = fmaf(st.w[t], gt.x, mr);
-                            mi = fmaf(st.w[t], gt.y, mi);
+                            for (int t = 0; t < kSincTaps; ++t) {
+                                const float2 gt = g[k][t * Q + q];
+                                mr = fmaf(pt[k].w[t], gt.x, mr);
+                                mi = fmaf(pt[k].w[t], gt.y, mi);
+                            }
                         }
-                        m[q][0] = mr;
-                        m[q][1] = mi;
-                    } else {
-                        const float2 g0 = g[q * Hs];
-                        m[q][0] = g0.x;
-                        m[q][1] = g0.y;
-                        if constexpr (kMode == GEOLOC_DELAY_LINEAR) {
-                            const float2 g1 = g[q * Hs + 1];
-                            m[q][0] = fmaf(st.alpha, g1.x - g0.x, g0.x);
-                            m[q][1] = fmaf(st.alpha, g1.y - g0.y, g0.y);
+                        // (j delta)^q / q! is real for even q, imaginary for odd q
+#pragma unroll
+                        for (int t = 0; t < kT; ++t) {
+                            float gr = mr, gi = mi;
+                            if constexpr (kMode != GEOLOC_DELAY_SINC) {
+                                const float2 gv = g[k][t * Q + q];
+                                gr = gv.x;
+                                gi = gv.y;
+                            }
+                            const float c = cf[k][t][q];
+                            if (q & 1) {
+                                sr = fmaf(-c, gi, sr);
+                                si = fmaf(c, gr, si);
+                            } else {
+                                sr = fmaf(c, gr, sr);
+                                si = fmaf(c, gi, si);
+                            }
                         }
                     }
+                    accr[k] = sr;
+                    acci[k] = si;
+                    g[k] += Hs * Q;
                 }
-                // s = sum_q (j delta)^q / q! m_q: even q real, odd q imaginary
-                float sr = m[0][0], si = m[0][1];
-#pragma unroll
-                for (int q = 1; q < Q; ++q) {
-                    if (q & 1) {
-                        sr = fmaf(-st.c[q], m[q][1], sr);
-                        si = fmaf(st.c[q], m[q][0], si);
-                    } else {
-                        sr = fmaf(st.c[q], m[q][0], sr);
-                        si = fmaf(st.c[q], m[q][1], si);
-                    }
-                }
-                cr = fmaf(W.x, sr, fmaf(-W.y, si, cr));
-                ci = fmaf(W.x, si, fmaf(W.y, sr, ci));
-                const float wr = fmaf(W.x, st.ERB.x, -(W.y * st.ERB.y));
-                W.y = fmaf(W.x, st.ERB.y, W.y * st.ERB.x);
-                W.x = wr;
             }
             __syncthreads();
+        }
+        // the exact weight of the tile's last block turns acc into this tile's share of C
+        const double t_last = (double)s0 + (double)(nblk - 1) * kFB + 0.5 * (double)(kFB - 1) - centre;
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            const float2 W = cis_cycles(pt[k].cyc * t_last);
+            cr[k] = fmaf(W.x, accr[k], fmaf(-W.y, acci[k], cr[k]));
+            ci[k] = fmaf(W.x, acci[k], fmaf(W.y, accr[k], ci[k]));
         }
     }
 }
 
-template <int kMode, int kQMax>   // GEOLOC_DELAY_LINEAR, _ROUND or _SINC; most Taylor terms
+// kMode: GEOLOC_DELAY_LINEAR, _ROUND or _SINC; kQMax: most Taylor terms; kPPT: points per
+// thread (tiles of 256 kPPT cells).
+template <int kMode, int kQMax, int kPPT>
 __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     __shared__ float2 s_y[kFT + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
-    __shared__ __align__(16) float2 s_G[kQMax * 512];   // [round block][q][lag], <= 512 (block, lag) slots
+    __shared__ __align__(16) float2 s_G[kQMax * 512];   // [round block][lag][q], <= 512 (block, lag) slots
     __shared__ float2 s_rot[kFB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
+    constexpr int kLanes = 256 * kPPT;
 
     const int tid = threadIdx.x;
     // workgroup -> (point tile, group of (pair, step) items, segment of the step)
@@ -236,10 +280,21 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
     const int64_t it_hi = n_items * (group + 1) / a.n_groups;
-    bool valid;
-    const int64_t p = tile_point(a.tiling, tile, tid, &valid);
-    double jacc = (valid && a.load_J && a.n_groups == 1) ? (double)a.J[p] : 0.0;
+    bool valid[kPPT];
+    int64_t p[kPPT];
+    double jacc[kPPT];
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k) {
+        p[k] = tile_point(a.tiling, tile, tid + 256 * k, &valid[k]);
+        jacc[k] = (valid[k] && a.load_J && a.n_groups == 1) ? (double)a.J[p[k]] : 0.0;
+    }
     const double two_pi = 6.283185307179586476925;
+    auto zero_cpart = [&](int64_t it) {
+        if (!segmented) return;
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k)
+            if (valid[k]) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p[k]] = make_float2(0.f, 0.f);
+    };
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
         const int e = (int)(it / a.kc);
@@ -247,28 +302,39 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
-        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
-        double D = valid ? a.D[gi] : 0.0;
-        const double nu = valid ? a.nu[gi] : 0.0;
-        if (!(fabs(D) < 1.0e9)) D = 1.0e9;
-        int d0;
-        float alpha;
-        if constexpr (kMode == GEOLOC_DELAY_ROUND) {
-            d0 = (int)round(D);
-            alpha = 0.f;
-        } else {
-            const double f = floor(D);
-            d0 = (int)f;
-            alpha = (float)(D - f);
+        FactPoint pt[kPPT];
+        int d0[kPPT];
+        float th[kPPT];
+        int dlo = INT_MAX, dhi = INT_MIN;
+        float tlo = FLT_MAX, thi = -FLT_MAX;
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kLanes + tid + 256 * k;
+            double D = valid[k] ? a.D[gi] : 0.0;
+            const double nu = valid[k] ? a.nu[gi] : 0.0;
+            // keep the integer lag representable whatever the geometry (NaN included)
+            if (!(fabs(D) < 1.0e9)) D = 1.0e9;
+            if constexpr (kMode == GEOLOC_DELAY_ROUND) {
+                d0[k] = (int)round(D);
+                pt[k].alpha = 0.f;
+            } else {
+                const double f = floor(D);
+                d0[k] = (int)f;
+                pt[k].alpha = (float)(D - f);
+            }
+            pt[k].cyc = nu * a.inv_fs;                    // cycles per sample
+            th[k] = (float)(two_pi * pt[k].cyc);          // radians per sample
+            if (valid[k]) {
+                dlo = min(dlo, d0[k]);
+                dhi = max(dhi, d0[k]);
+                tlo = fminf(tlo, th[k]);
+                thi = fmaxf(thi, th[k]);
+            }
         }
-        const double cyc = nu * a.inv_fs;             // cycles per sample
-        const float th = (float)(two_pi * cyc);       // radians per sample
-        int dlo = valid ? d0 : INT_MAX, dhi = valid ? d0 : INT_MIN;
-        float tlo = valid ? th : FLT_MAX, thi = valid ? th : -FLT_MAX;
         wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
         if (dhi < dlo) {                               // no grid cell in this tile: nothing to add
             if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = 0;
-            if (segmented && valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(0.f, 0.f);
+            zero_cpart(it);
             continue;
         }
         const int64_t spread = (int64_t)dhi - (int64_t)dlo;
@@ -292,7 +358,7 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         const bool fact = Q > 0 && spread + kTaps <= kFH;
         if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
         if (!fact) {                                   // uniform: the per-point kernel takes it
-            if (segmented && valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(0.f, 0.f);
+            zero_cpart(it);
             continue;
         }
 
@@ -300,20 +366,19 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         const int H = (int)spread + kTaps;
         const int Hg = (H + 1) / 2;                    // lag pairs
         st.n_step = (int64_t)(a.k0 + kk) * a.L;
-        st.cyc = cyc;
-        st.ERB = cis_cycles(cyc * (double)kFB);
-        st.alpha = alpha;
-        if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(alpha, st.w);
-        // the Taylor coefficients (j delta)^q / q! are real or imaginary in turn
-        const float dl = (float)(two_pi * cyc - (double)tbar);
-        {
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            pt[k].ERB = cis_cycles(pt[k].cyc * (double)kFB);
+            if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(pt[k].alpha, pt[k].w);
             // (j dl)^q / q! = j^q dl^q / q!: j^q is 1, j, -1, -j in turn
+            const float dl = (float)(two_pi * pt[k].cyc - (double)tbar);
             float t = 1.f;
 #pragma unroll
             for (int q = 0; q < kFQWide; ++q) {
-                st.c[q] = ((q & 2) ? -t : t);
+                pt[k].c[q] = ((q & 2) ? -t : t);
                 t *= dl / (float)(q + 1);
             }
+            pt[k].off = valid[k] ? d0[k] - dlo : 0;
         }
         st.dlo = dlo - kTapLo;
         st.Hs = 2 * Hg;
@@ -321,7 +386,6 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         st.TB = st.NB * (kFTB / st.NB);
         st.my_b = tid / Hg;
         st.my_l = 2 * (tid - st.my_b * Hg);
-        st.off = valid ? d0 - dlo : 0;
         st.seg_lo = segmented ? seg * a.seg_len : 0;
         st.seg_hi = segmented ? min(a.L, (seg + 1) * a.seg_len) : a.L;
         if (tid < kFB) {
@@ -329,27 +393,36 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
             sincosf(tbar * ((float)tid - 0.5f * (float)(kFB - 1)), &sn, &cs);
             s_rot[tid] = make_float2(cs, sn);
         }
-        float cr = 0.f, ci = 0.f;
+        float cr[kPPT], ci[kPPT];
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) cr[k] = ci[k] = 0.f;
         switch (Q) {
-            case 1: fact_step<kMode, 1>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 2: fact_step<kMode, 2>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 3: fact_step<kMode, 3>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 4: fact_step<kMode, 4>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4)>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
-            default: fact_step<kMode, kQMax>(a, yi, yj, st, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 1: fact_step<kMode, 1, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 2: fact_step<kMode, 2, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kMode, 3, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 4: fact_step<kMode, 4, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4), kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kMode, kQMax, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
         }
-        if (segmented) {
-            if (valid) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p] = make_float2(cr, ci);
-            continue;
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            if (segmented) {
+                if (valid[k]) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p[k]] = make_float2(cr[k], ci[k]);
+            } else {
+                const double pw = (double)cr[k] * cr[k] + (double)ci[k] * ci[k];
+                jacc[k] += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
+            }
         }
-        const double pw = (double)cr * cr + (double)ci * ci;
-        jacc += (a.accum_mode == GEOLOC_ACC_MAG) ? sqrt(pw) : pw;
     }
-    if (!valid || segmented) return;
-    if (a.n_groups == 1)
-        a.J[p] = (float)jacc;
-    else
-        a.partial[(int64_t)group * a.P + p] = jacc;
+    if (segmented) return;
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k) {
+        if (!valid[k]) continue;
+        if (a.n_groups == 1)
+            a.J[p[k]] = (float)jacc[k];
+        else
+            a.partial[(int64_t)group * a.P + p[k]] = jacc[k];
+    }
 }
 
 // J[p] = (J[p] if loading) + sum over items of |sum over segments of cpart|^2 (or |.|), in a
@@ -380,23 +453,32 @@ hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int kQMax>
+template <int kQMax, int kPPT>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT>), grid, block, 0, s, a, deferred);
     else if (delay_mode == GEOLOC_DELAY_SINC)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT>), grid, block, 0, s, a, deferred);
     else
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT>), grid, block, 0, s, a, deferred);
 }
 
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               hipStream_t s) {
-    if (wide_doppler)
-        launch_fact_q<kFQWide>(a, deferred, delay_mode, s);
-    else
-        launch_fact_q<kFQ>(a, deferred, delay_mode, s);
+    const int lanes = tile_lanes(a.tiling);
+    if (lanes != 256 && lanes != 512) return hipErrorInvalidValue;
+    if (lanes == 512) {
+        if (wide_doppler)
+            launch_fact_q<kFQWide, 2>(a, deferred, delay_mode, s);
+        else
+            launch_fact_q<kFQ, 2>(a, deferred, delay_mode, s);
+    } else {
+        if (wide_doppler)
+            launch_fact_q<kFQWide, 1>(a, deferred, delay_mode, s);
+        else
+            launch_fact_q<kFQ, 1>(a, deferred, delay_mode, s);
+    }
     return hipGetLastError();
 }
 

@@ -16,13 +16,17 @@ constexpr int kSincAnchor = 64;   // samples between FP64 phase re-anchors
 
 __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x % a.n_tiles;
-    const int group = (int)(blockIdx.x / a.n_tiles);
+    // (a tile of 512 cells is two workgroups, one per half)
+    const int halves = tile_lanes(a.tiling) / 256;
+    const int64_t sub = blockIdx.x % (a.n_tiles * halves);
+    const int64_t tile = sub / halves;
+    const int lane = (int)(sub - tile * halves) * 256 + tid;
+    const int group = (int)(blockIdx.x / (a.n_tiles * halves));
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
     const int64_t it_hi = n_items * (group + 1) / a.n_groups;
     bool valid;
-    const int64_t p = tile_point(a.tiling, tile, tid, &valid);
+    const int64_t p = tile_point(a.tiling, tile, lane, &valid);
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
     if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
@@ -38,7 +42,7 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kTilePoints + tid;
+        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * (halves * 256) + lane;
         double D = a.D[gi];
         const double nu = a.nu[gi];
         if (!(fabs(D) < 1.0e9)) D = 1.0e9;
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
 }
 
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s) {
-    dim3 grid((unsigned)(a.n_tiles * a.n_groups)), block(256);
+    dim3 grid((unsigned)(a.n_tiles * (tile_lanes(a.tiling) / 256) * a.n_groups)), block(256);
     hipLaunchKernelGGL(k_direct_sinc, grid, block, 0, s, a);
     return hipGetLastError();
 }

@@ -35,11 +35,12 @@ __global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ la
 }
 
 // One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
-// Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * 256 + lane, with the point of
+// Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * lanes + lane, with the point of
 // (tile, lane) as in the correlation kernels; lanes past the grid edge write zeros.
 __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * kTilePoints : a.P;
+    const int64_t lanes = tile_lanes(a.tiling);
+    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * lanes : a.P;
     const int64_t total = per_step * a.kc * a.n_pairs;
     if (idx >= total) return;
     const int64_t within = idx % per_step;
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
     int64_t p = within;
     if (a.tile_major) {
         bool valid;
-        p = tile_point(a.tiling, within / kTilePoints, (int)(within % kTilePoints), &valid);
+        p = tile_point(a.tiling, within / lanes, (int)(within % lanes), &valid);
         if (!valid) {
             a.D[idx] = 0.0;
             a.nu[idx] = 0.0;
@@ -75,7 +76,8 @@ hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_k
 }
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s) {
-    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * kTilePoints : a.P;
+    const int64_t lanes = tile_lanes(a.tiling);
+    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * lanes : a.P;
     const int64_t total = per_step * a.kc * a.n_pairs;
     dim3 grid((unsigned)((total + 255) / 256));
     hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, s, a);
