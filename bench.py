@@ -322,7 +322,10 @@ def delay_modes_leg(geoloc, torch, scn, caps):
             e1.record()
             torch.cuda.synchronize()
             idx, val = plan.argmax(J)
-        out[name] = {"map_ms": e0.elapsed_time(e1), "peak": float(val[0]), "argmax": int(idx[0])}
+            info = plan.info()
+        out[name] = {"map_ms": e0.elapsed_time(e1), "peak": float(val[0]), "argmax": int(idx[0]),
+                     "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f}"
+                             f"{' transposed' if info['tile_transpose'] else ''}"}
     for name in ("linear", "round"):
         out[name]["peak_vs_sinc"] = out[name]["peak"] / out["sinc"]["peak"]
     return out

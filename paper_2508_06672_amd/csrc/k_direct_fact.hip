@@ -167,14 +167,20 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
         {
             const int64_t m0 = st.n_step + s0 + st.dlo;
             const int len = nblk * kFB + Hs;
-            for (int t = tid; t < len; t += 256) {
-                const int64_t m = m0 + t;
-                s_y[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
+            if (m0 >= 0 && m0 + len <= a.N) {          // uniform: the usual case, no bounds checks
+                const float2* __restrict__ ys = yj + m0;
+                for (int t = tid; t < len; t += 256) s_y[t] = ys[t];
+            } else {
+                for (int t = tid; t < len; t += 256) {
+                    const int64_t m = m0 + t;
+                    s_y[t] = (m >= 0 && m < a.N) ? yj[m] : make_float2(0.f, 0.f);
+                }
             }
+            const float2* __restrict__ xs = yi + st.n_step + s0;
             for (int t = tid; t < nblk * kFB; t += 256) {
                 float2 v = make_float2(0.f, 0.f);
                 if (t < tl) {
-                    const float2 x = yi[st.n_step + s0 + t];
+                    const float2 x = xs[t];
                     const float2 rt = s_rot[t & (kFB - 1)];
                     v = make_float2(x.x * rt.x - x.y * rt.y, x.x * rt.y + x.y * rt.x);
                 }
@@ -296,12 +302,31 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
             if (valid[k]) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p[k]] = make_float2(0.f, 0.f);
     };
 
+    // this item's delays and Doppler shifts, loaded one item ahead (item it is entry
+    // it * n_tiles + tile of the tile-major table, it = e * kc + kk)
+    double nD[kPPT], nnu[kPPT];
+    auto fetch = [&](int64_t it) {
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            const int64_t gi = (it * a.n_tiles + tile) * kLanes + tid + 256 * k;
+            nD[k] = (valid[k] && it < it_hi) ? a.D[gi] : 0.0;
+            nnu[k] = (valid[k] && it < it_hi) ? a.nu[gi] : 0.0;
+        }
+    };
+    fetch(it_lo);
     for (int64_t it = it_lo; it < it_hi; ++it) {
         const int e = (int)(it / a.kc);
         const int kk = (int)(it - (int64_t)e * a.kc);
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
+        double cD[kPPT], cnu[kPPT];
+#pragma unroll
+        for (int k = 0; k < kPPT; ++k) {
+            cD[k] = nD[k];
+            cnu[k] = nnu[k];
+        }
+        fetch(it + 1);
         FactPoint pt[kPPT];
         int d0[kPPT];
         float th[kPPT];
@@ -309,9 +334,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         float tlo = FLT_MAX, thi = -FLT_MAX;
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
-            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * kLanes + tid + 256 * k;
-            double D = valid[k] ? a.D[gi] : 0.0;
-            const double nu = valid[k] ? a.nu[gi] : 0.0;
+            double D = cD[k];
+            const double nu = cnu[k];
             // keep the integer lag representable whatever the geometry (NaN included)
             if (!(fabs(D) < 1.0e9)) D = 1.0e9;
             if constexpr (kMode == GEOLOC_DELAY_ROUND) {
@@ -376,7 +400,7 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
 #pragma unroll
             for (int q = 0; q < kFQWide; ++q) {
                 pt[k].c[q] = ((q & 2) ? -t : t);
-                t *= dl / (float)(q + 1);
+                t *= dl * (1.f / (float)(q + 1));
             }
             pt[k].off = valid[k] ? d0[k] - dlo : 0;
         }
