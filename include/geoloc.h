@@ -211,6 +211,24 @@ int geoloc_caf_table(geoloc_plan_t plan, const geoloc_inputs* in, int32_t pair_i
 int geoloc_argmax(geoloc_plan_t plan, const float* J_dev, int32_t top_k, int32_t nms_radius_cells,
                   int64_t* idx_host, float* val_host, void* stream);
 
+/* Threshold detection of several emitters (the threshold step of Algorithm 1, which the
+ * paper leaves open), read as cell-averaging CFAR on a RECT map J_dev[rows][cols]: the noise
+ * level of a cell is the mean of J over the cells within Chebyshev distance train_cells of
+ * it, clipped to the grid, less those within guard_cells (0 <= guard < train); the cell is a
+ * detection when J > scale x that mean. The detections are reported as peaks, largest
+ * first (ties to the lowest flat index), each excluding a (2r+1) x (2r+1) window around it
+ * (r = nms_radius_cells) as in geoloc_argmax, at most max_detections (1 .. 64) of them.
+ * For independent Gamma(L) noise cells and N training cells, scale = N b / (1 - b) with b
+ * the (1 - Pfa) quantile of Beta(L, N L) gives false-alarm probability Pfa (L = 1:
+ * scale = N (Pfa^(-1/N) - 1)). idx_host / val_host / noise_host are HOST arrays of
+ * max_detections entries (flat index, J, noise mean; unused entries -1, -inf, 0) and
+ * *n_found the number of detections. The plan allocates 16 bytes per grid point of scratch
+ * on the first call. Synchronises `stream`. Errors: EINVAL (POINTS grid, bad window, scale
+ * or count), ENAN (a NaN in J), ENOMEM, ELAUNCH. */
+int geoloc_detect(geoloc_plan_t plan, const float* J_dev, int32_t guard_cells, int32_t train_cells, double scale,
+                  int32_t max_detections, int32_t nms_radius_cells, int64_t* idx_host, float* val_host,
+                  float* noise_host, int32_t* n_found, void* stream);
+
 int geoloc_info(geoloc_plan_t plan, geoloc_plan_info* out);
 
 /* Release the plan and its device scratch (synchronises the device first). */

@@ -77,6 +77,11 @@ struct geoloc_plan_s {
     bool fact_wide = false;          // its variant with up to 6 Taylor terms (wide Doppler spreads)
     int32_t n_segs = 1, seg_len = 0; // factored kernel: coherent segments per step (few tiles, long steps)
     float2* d_cpart = nullptr;       // [n_segs][n_pairs * kc][P] complex partial sums
+    // detection (allocated by the first geoloc_detect)
+    double* d_sat = nullptr;         // [rows][cols] summed-area table of J
+    float* d_masked = nullptr;       // [P] J where a detection, -inf elsewhere
+    float* d_noise = nullptr;        // [P] training-window mean
+    float* d_found_noise = nullptr;  // [kMaxTopK]
     ArgmaxScratch am;
     int64_t device_bytes = 0;
     // host staging for receiver states (pinned) and its reuse guard
@@ -152,6 +157,10 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->d_nu);
     (void)hipFree(p->d_partial);
     (void)hipFree(p->d_cpart);
+    (void)hipFree(p->d_sat);
+    (void)hipFree(p->d_masked);
+    (void)hipFree(p->d_noise);
+    (void)hipFree(p->d_found_noise);
     (void)hipFree(p->d_deferred);
     (void)hipFree(p->am.part_val);
     (void)hipFree(p->am.part_idx);
@@ -1050,6 +1059,46 @@ int geoloc_argmax(geoloc_plan_t p, const float* J, int32_t top_k, int32_t radius
         idx_host[t] = idx[t];
         val_host[t] = idx[t] < 0 ? -INFINITY : val[t];
     }
+    return GEOLOC_OK;
+}
+
+int geoloc_detect(geoloc_plan_t p, const float* J, int32_t guard, int32_t train, double scale, int32_t max_det,
+                  int32_t radius, int64_t* idx_host, float* val_host, float* noise_host, int32_t* n_found,
+                  void* stream) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (!J || !idx_host || !val_host || !noise_host || !n_found) return fail(GEOLOC_EINVAL, "NULL pointer");
+    if (p->grid_kind != GEOLOC_GRID_RECT) return fail(GEOLOC_EINVAL, "detection needs a RECT grid");
+    if (guard < 0 || train <= guard) return fail(GEOLOC_EINVAL, "need 0 <= guard < train");
+    if (max_det < 1 || max_det > kMaxTopK) return fail(GEOLOC_EINVAL, "max_detections must be in [1, %d]", kMaxTopK);
+    if (radius < 0) return fail(GEOLOC_EINVAL, "exclusion radius < 0");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(GEOLOC_EINVAL, "scale must be finite and > 0");
+    int rc = GEOLOC_OK;
+    if (!p->d_sat) {
+        if ((rc = dev_alloc(p, &p->d_sat, (size_t)p->P))) return rc;
+        if ((rc = dev_alloc(p, &p->d_masked, (size_t)p->P))) return rc;
+        if ((rc = dev_alloc(p, &p->d_noise, (size_t)p->P))) return rc;
+        if ((rc = dev_alloc(p, &p->d_found_noise, (size_t)kMaxTopK))) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_cfar(J, p->rows, p->cols, guard, train, scale, p->d_sat, p->d_masked, p->d_noise, s));
+    HIP_TRY(launch_argmax(p->d_masked, p->P, p->cols, 1, radius, max_det, p->am, s));
+    HIP_TRY(launch_gather_noise(p->d_noise, p->am.found_idx, max_det, p->d_found_noise, s));
+    std::vector<int64_t> idx(max_det);
+    std::vector<float> val(max_det), nz(max_det);
+    HIP_TRY(hipMemcpyAsync(idx.data(), p->am.found_idx, max_det * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(val.data(), p->am.found_val, max_det * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(nz.data(), p->d_found_noise, max_det * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (std::isnan(val[0])) return fail(GEOLOC_ENAN, "NaN in map");
+    int32_t n = 0;
+    for (int t = 0; t < max_det; ++t) {
+        const bool ok = idx[t] >= 0 && val[t] > -INFINITY;   // masked cells are not detections
+        idx_host[t] = ok ? idx[t] : -1;
+        val_host[t] = ok ? val[t] : -INFINITY;
+        noise_host[t] = ok ? nz[t] : 0.f;
+        if (ok) ++n;
+    }
+    *n_found = n;
     return GEOLOC_OK;
 }
 

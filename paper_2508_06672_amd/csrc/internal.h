@@ -134,6 +134,11 @@ hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t de
                               hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
 // J[p] = (J[p] if loading) + sum over items of |sum over segments of cpart|^2 (or |.|)
+// CFAR detection (k_cfar.hip): summed-area table of J in sat [rows][cols], then masked[p] =
+// J[p] where J exceeds scale x the training-window mean (noise[p]), -inf elsewhere.
+hipError_t launch_cfar(const float* J, int64_t rows, int64_t cols, int32_t guard, int32_t train, double scale,
+                       double* sat, float* masked, float* noise, hipStream_t s);
+hipError_t launch_gather_noise(const float* noise, const int64_t* idx, int32_t k, float* out, hipStream_t s);
 hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s);
 
 constexpr int32_t kMaxItemGroups = 64;

@@ -97,6 +97,9 @@ def load() -> ctypes.CDLL:
     lib.geoloc_caf_table.argtypes = [_vp, P(geoloc_inputs), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _vp,
                                      ctypes.c_int64]
     lib.geoloc_argmax.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), _vp]
+    lib.geoloc_detect.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), P(ctypes.c_float),
+                                  P(ctypes.c_int32), _vp]
     lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
     lib.geoloc_destroy.argtypes = [_vp]
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
@@ -104,7 +107,7 @@ def load() -> ctypes.CDLL:
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
-                 "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
+                 "geoloc_detect", "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -187,6 +190,34 @@ def geoloc_argmax(plan: int, J_dev: int, top_k: int, nms_radius: int, stream: in
                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream), "geoloc_argmax")
     return idx, val
+
+
+def geoloc_detect(plan: int, J_dev: int, guard: int, train: int, scale: float, max_detections: int, nms_radius: int,
+                  stream: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    idx = np.empty(max_detections, dtype=np.int64)
+    val = np.empty(max_detections, dtype=np.float32)
+    noise = np.empty(max_detections, dtype=np.float32)
+    n = ctypes.c_int32(0)
+    _check(load().geoloc_detect(plan, J_dev, guard, train, float(scale), max_detections, nms_radius,
+                                idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                noise.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n),
+                                stream), "geoloc_detect")
+    return idx[:n.value], val[:n.value], noise[:n.value]
+
+
+def cfar_scale(pfa: float, n_train: int, looks: int = 1) -> float:
+    """CFAR scale for false-alarm probability pfa with n_train training cells of independent
+    Gamma(looks) noise: the cell x and the training sum z give x / (x + z) ~ Beta(looks,
+    n_train looks), so scale = n_train b / (1 - b) with b its (1 - pfa) quantile."""
+    from scipy.special import betaincinv
+    b = float(betaincinv(looks, n_train * looks, 1.0 - pfa))
+    return n_train * b / (1.0 - b)
+
+
+def cfar_training_cells(guard: int, train: int) -> int:
+    """Training cells of an interior grid cell."""
+    return (2 * train + 1) ** 2 - (2 * guard + 1) ** 2
 
 
 def geoloc_info(plan: int) -> geoloc_plan_info:
@@ -324,6 +355,12 @@ class Plan:
 
     def argmax(self, J, top_k: int = 1, nms_radius: int = 0, stream=None):
         return geoloc_argmax(self.handle, J.data_ptr(), top_k, nms_radius, _stream_handle(stream))
+
+    def detect(self, J, guard: int, train: int, scale: float, max_detections: int = 16, nms_radius: int = 0,
+               stream=None):
+        """CFAR detections of a RECT map: (flat indices, J values, noise means), largest first."""
+        return geoloc_detect(self.handle, J.data_ptr(), guard, train, scale, max_detections, nms_radius,
+                             _stream_handle(stream))
 
     def set_grid(self, lat, lon) -> None:
         lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()

@@ -1,0 +1,93 @@
+"""CFAR detection of several emitters (threshold step of Algorithm 1) on the GPU against the
+oracle: planted peaks on Gamma noise maps (detections, values and noise means), a map with
+no detection, ragged windows at the grid edges, and the error paths."""
+import numpy as np
+import pytest
+
+from oracle import cfar as ocfar
+from helpers import log, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2508_06672_amd import geoloc
+    geoloc.load()
+    return geoloc
+
+
+def _plan(G, rows, cols):
+    lat = np.linspace(0.30, 0.30 + 1e-4 * rows, rows)
+    lon = np.linspace(-0.20, -0.20 + 1e-4 * cols, cols)
+    return G.Plan(n_rx=2, n_samples=1000, step_len=1000, fs_hz=1e6, fc_hz=1.5e9, lat=lat, lon=lon)
+
+
+def _map(rows, cols, looks, seed, peaks):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    J = rng.gamma(looks, 3.0, size=(rows, cols))
+    rr, cc = np.mgrid[0:rows, 0:cols]
+    for (r, c, h) in peaks:
+        J += h * np.exp(-((rr - r) ** 2 + (cc - c) ** 2) / 1.0)
+    return J.astype(np.float32)
+
+
+def _check(det_g, det_o, J, guard, train, scale):
+    idx, val, noise = det_g
+    assert [i for i, _, _ in det_o] == list(idx)
+    assert np.array_equal(np.array([v for _, v, _ in det_o], dtype=np.float32), val)
+    assert np.allclose(noise, [n for _, _, n in det_o], rtol=2e-6, atol=0)
+    # decisions are compared where they are not within rounding of the threshold
+    nz, n = ocfar.noise_estimate(J.astype(np.float64), guard, train)
+    margin = np.abs(J.astype(np.float64) - scale * nz) / np.maximum(scale * nz, 1e-300)
+    assert np.min(margin) > 1e-9
+
+
+@pytest.mark.parametrize("rows,cols,looks,guard,train,radius", [(120, 170, 8, 2, 6, 4), (61, 45, 1, 1, 3, 2),
+                                                              (300, 257, 4, 3, 9, 6)])
+def test_detect_matches_oracle(torch, G, rows, cols, looks, guard, train, radius):
+    peaks = [(10, 12, 900.0), (rows // 2, cols // 2, 400.0), (rows - 3, cols - 20, 250.0), (rows // 3, 5, 150.0)]
+    J = _map(rows, cols, looks, rows * 1000 + cols, peaks)
+    N = G.cfar_training_cells(guard, train)
+    scale = G.cfar_scale(1e-6, N, looks)
+    log(f"detect {rows}x{cols} looks {looks} guard {guard} train {train} scale {scale:.3f}")
+    det_o = ocfar.detect(J.astype(np.float64), guard, train, scale, 16, radius)
+    with _plan(G, rows, cols) as plan:
+        det_g = plan.detect(torch.from_numpy(J).cuda(), guard, train, scale, 16, radius)
+    log(f"  {len(det_g[0])} detections: {list(det_g[0])}")
+    _check(det_g, det_o, J, guard, train, scale)
+    found = {divmod(int(i), cols) for i in det_g[0]}
+    assert {(r, c) for r, c, _ in peaks} <= found
+
+
+def test_no_detection_and_limits(torch, G):
+    rows, cols = 40, 50
+    J = np.full((rows, cols), 2.0, dtype=np.float32)
+    with _plan(G, rows, cols) as plan:
+        Jd = torch.from_numpy(J).cuda()
+        idx, val, noise = plan.detect(Jd, 1, 4, 1.5, 8, 2)
+        assert idx.size == 0
+        # one cell above a flat floor: detected with the floor as its noise mean
+        J[0, 0] = 5.0
+        idx, val, noise = plan.detect(torch.from_numpy(J).cuda(), 1, 4, 1.5, 8, 2)
+        assert list(idx) == [0] and val[0] == 5.0 and noise[0] == pytest.approx(2.0)
+        for bad in [(2, 2, 1.0, 8, 1), (-1, 3, 1.0, 8, 1), (1, 3, 0.0, 8, 1), (1, 3, 1.0, 0, 1), (1, 3, 1.0, 65, 1),
+                    (1, 3, float("nan"), 8, 1), (1, 3, 1.0, 8, -1)]:
+            with pytest.raises(G.GeolocError) as ei:
+                plan.detect(Jd, *bad)
+            assert ei.value.status == G.EINVAL, bad
+        J[5, 7] = np.nan
+        with pytest.raises(G.GeolocError) as ei:
+            plan.detect(torch.from_numpy(J).cuda(), 1, 4, 1.5, 8, 2)
+        assert ei.value.status == G.ENAN
+    pts = G.Plan(n_rx=2, n_samples=1000, step_len=1000, fs_hz=1e6, fc_hz=1.5e9, lat=np.full(300, 0.3),
+                 lon=np.linspace(0, 0.01, 300), grid_kind=G.GRID_POINTS)
+    with pts:
+        with pytest.raises(G.GeolocError) as ei:
+            pts.detect(torch.zeros(300, device="cuda"), 1, 3, 1.0, 4, 0)
+        assert ei.value.status == G.EINVAL
