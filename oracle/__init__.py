@@ -6,13 +6,15 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 Contents
   * ``geoloc_oracle.c`` (built to ``liboracle.so`` with gcc, -O2 -fopenmp
-    -ffp-contract=off): grid -> ECEF, geometry (Eq. (3)-(9)), one correlation
+    -ffp-contract=off): grid -> ECEF (sphere, or the WGS-84 ellipsoid with a
+    height per point), geometry (Eq. (3)-(9)), one correlation
     (Eq. (11)) with a ROUND, LINEAR or eight-tap windowed-sinc delay, the full map
     (Algorithm 1, accumulated over steps and pairs).
   * ``caf.py``: the FP64 CAF-table form of Eq. (11) (lag-product matrix times a
     Doppler phasor matrix, then bilinear interpolation in lag and Doppler).
   * ``brute.py``: Eq. (11) written as literal Python loops, for tiny inputs.
   * ``peaks.py``: argmax / top-k with non-maximum suppression.
+  * ``cfar.py``: cell-averaging CFAR detection of several emitters.
   * ``cnn.py``: FP64 forward / backward / Adam of the tile-proposal CNN.
 """
 from __future__ import annotations
@@ -48,6 +50,8 @@ def _load():
         lib.oracle_corr.argtypes = [fp, fp, i64, i64, i64, f64, f64, f64, i32, dp, dp]
         lib.oracle_map.argtypes = [i64, dp, dp, f64, f64, i32, i64, i64, fp, dp, i32, ip, f64, f64, i32, i32, dp]
         lib.oracle_sinc_taps.argtypes = [f64, dp]
+        lib.oracle_ecef_wgs84.argtypes = [i64, dp, dp, dp, dp]
+        lib.oracle_map_xyz.argtypes = [i64, dp, i32, i64, i64, fp, dp, i32, ip, f64, f64, i32, i32, dp]
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -109,6 +113,36 @@ def grid_ecef(lat, lon, radius: float = 6371.0e3, alt: float = 0.0) -> np.ndarra
     out = np.empty((lat.size, 3))
     _load().oracle_grid_ecef(lat.size, _dptr(lat), _dptr(lon), radius, alt, _dptr(out))
     return out
+
+
+def ecef_wgs84(lat, lon, h) -> np.ndarray:
+    """Geodetic latitude / longitude (radians) and height above the WGS-84 ellipsoid (m,
+    one per point or a scalar) to ECEF [n][3]."""
+    lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
+    lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), lat.shape))
+    out = np.empty((lat.size, 3))
+    _load().oracle_ecef_wgs84(lat.size, _dptr(lat), _dptr(lon), _dptr(h), _dptr(out))
+    return out
+
+
+def map_xyz(xyz, captures: np.ndarray, states: np.ndarray, step_len: int, fs: float, fc: float,
+            pairs: Optional[Sequence[Tuple[int, int]]] = None, delay_mode: int = LINEAR,
+            accum_mode: int = POWER) -> np.ndarray:
+    """J at candidate points given in ECEF (m)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    caps = np.ascontiguousarray(captures, dtype=np.complex64)
+    R, N = caps.shape
+    if pairs is None:
+        pairs = [(i, j) for i in range(R) for j in range(i + 1, R)]
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    st = np.ascontiguousarray(states, dtype=np.float64)
+    assert st.shape == (N // step_len, R, 6)
+    J = np.empty(xyz.shape[0])
+    _load().oracle_map_xyz(xyz.shape[0], _dptr(xyz), R, N, step_len, _fptr(caps.view(np.float32)), _dptr(st),
+                           pr.shape[0], pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), fs, fc, delay_mode,
+                           accum_mode, _dptr(J))
+    return J
 
 
 def geometry(xyz: np.ndarray, states: np.ndarray, pair: Tuple[int, int], fs: float, fc: float):

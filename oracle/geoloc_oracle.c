@@ -66,6 +66,23 @@ void oracle_grid_ecef(int64_t n, const double* lat, const double* lon, double ra
     }
 }
 
+/* Candidate point on the WGS-84 ellipsoid (geodetic lat, lon in radians; height h[p] above
+ * the ellipsoid along its normal, e.g. a terrain model) to ECEF: with the prime-vertical
+ * radius of curvature N = a / sqrt(1 - e^2 sin^2 lat),
+ *   x = (N + h) cos lat cos lon, y = (N + h) cos lat sin lon, z = (N (1 - e^2) + h) sin lat,
+ * a = 6378137 m, f = 1 / 298.257223563, e^2 = f (2 - f). */
+void oracle_ecef_wgs84(int64_t n, const double* lat, const double* lon, const double* h, double* xyz) {
+    const double a = 6378137.0, f = 1.0 / 298.257223563;
+    const double e2 = f * (2.0 - f);
+    for (int64_t p = 0; p < n; ++p) {
+        double sl = sin(lat[p]), cl = cos(lat[p]);
+        double N = a / sqrt(1.0 - e2 * sl * sl);
+        xyz[3 * p + 0] = (N + h[p]) * cl * cos(lon[p]);
+        xyz[3 * p + 1] = (N + h[p]) * cl * sin(lon[p]);
+        xyz[3 * p + 2] = (N * (1.0 - e2) + h[p]) * sl;
+    }
+}
+
 /* Delay and Doppler of one receiver state s = [p; v] against point q: Eq. (3)-(6). */
 static void receiver_delay_doppler(const double q[3], const double* s, double lambda,
                                    double* tau, double* f) {
@@ -195,15 +212,37 @@ void oracle_corr(const float* yi, const float* yj, int64_t n_samples, int64_t k,
  *   captures: [n_rx][N] interleaved complex64; states: [K][n_rx][6];
  *   pairs: [n_pairs][2] (reference i, shifted j); lat/lon: [n_points] (radians).
  *   J: [n_points] float64 (overwritten). */
+static double point_J(const double q[3], int32_t n_rx, int64_t n_samples, int64_t step_len, const float* captures,
+                      const double* states, int32_t n_pairs, const int32_t* pairs, double fs, double fc,
+                      int32_t delay_mode, int32_t accum_mode);
+
 void oracle_map(int64_t n_points, const double* lat, const double* lon, double radius, double alt,
                 int32_t n_rx, int64_t n_samples, int64_t step_len, const float* captures,
                 const double* states, int32_t n_pairs, const int32_t* pairs, double fs, double fc,
                 int32_t delay_mode, int32_t accum_mode, double* J) {
-    int64_t n_steps = n_samples / step_len;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t p = 0; p < n_points; ++p) {
         double q[3];
         oracle_grid_ecef(1, &lat[p], &lon[p], radius, alt, q);
+        J[p] = point_J(q, n_rx, n_samples, step_len, captures, states, n_pairs, pairs, fs, fc, delay_mode, accum_mode);
+    }
+}
+
+/* The same map at candidate points given in ECEF (xyz: [n_points][3], m). */
+void oracle_map_xyz(int64_t n_points, const double* xyz, int32_t n_rx, int64_t n_samples, int64_t step_len,
+                    const float* captures, const double* states, int32_t n_pairs, const int32_t* pairs, double fs,
+                    double fc, int32_t delay_mode, int32_t accum_mode, double* J) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < n_points; ++p)
+        J[p] = point_J(&xyz[3 * p], n_rx, n_samples, step_len, captures, states, n_pairs, pairs, fs, fc, delay_mode,
+                       accum_mode);
+}
+
+static double point_J(const double q[3], int32_t n_rx, int64_t n_samples, int64_t step_len, const float* captures,
+                      const double* states, int32_t n_pairs, const int32_t* pairs, double fs, double fc,
+                      int32_t delay_mode, int32_t accum_mode) {
+    int64_t n_steps = n_samples / step_len;
+    {
         double acc = 0.0;
         for (int32_t e = 0; e < n_pairs; ++e) {
             int32_t i = pairs[2 * e], j = pairs[2 * e + 1];
@@ -217,6 +256,6 @@ void oracle_map(int64_t n_points, const double* lat, const double* lon, double r
                 acc += (accum_mode == ORC_MAG) ? sqrt(pw) : pw;
             }
         }
-        J[p] = acc;
+        return acc;
     }
 }

@@ -1,7 +1,7 @@
 """Plant plausible mistakes in the oracle's C source (on the CPU) and check that the pins
 catch every one: a wrong sign, a swapped weight, a missing conjugate, an index off by one,
 broken zero padding, a swapped accumulation mode, a wrong coordinate, unnormalised or
-shifted windowed-sinc taps."""
+shifted windowed-sinc taps, a wrong WGS-84 radius of curvature, polar axis or height."""
 import os
 import subprocess
 
@@ -30,6 +30,10 @@ MUTANTS = {
                                "for (int i = 0; i < 2 * ORC_SINC_HALF; ++i) w[i] /= 1.0;"),
     "sinc_tap_offset": ("sample_at(yj, n_samples, n + d0 + t, &cr, &ci);",
                         "sample_at(yj, n_samples, n + d0 + t + 1, &cr, &ci);"),
+    "wgs84_prime_vertical_radius": ("double N = a / sqrt(1.0 - e2 * sl * sl);", "double N = a / sqrt(1.0 - e2 * cl * cl);"),
+    "wgs84_z_without_eccentricity": ("xyz[3 * p + 2] = (N * (1.0 - e2) + h[p]) * sl;", "xyz[3 * p + 2] = (N + h[p]) * sl;"),
+    "wgs84_height_not_along_normal": ("xyz[3 * p + 0] = (N + h[p]) * cl * cos(lon[p]);",
+                                      "xyz[3 * p + 0] = (N * cl + h[p]) * cos(lon[p]);"),
 }
 
 PINS = [getattr(pins, n) for n in dir(pins) if n.startswith("test_") and n != "test_peaks_rules"]

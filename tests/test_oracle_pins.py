@@ -471,3 +471,72 @@ def test_p16_sinc_caf_on_bin_equals_direct():
             dnu = nu_b[1] - nu_b[0]
             c_caf = caf.interp(T, lag_lo, nu_b[0], dnu, np.array([D]), np.array([nu_b[m]]), oracle.SINC)[0]
             assert abs(c_caf - c_dir) <= 1e-9 * max(1.0, abs(c_dir)), (k, D, m)
+
+
+# WGS-84 ellipsoid (the grid -> ECEF step with a terrain height per point)
+WGS_A = 6378137.0
+WGS_F = 1.0 / 298.257223563
+WGS_B = WGS_A * (1.0 - WGS_F)
+
+
+def test_p17_wgs84_closed_forms():
+    """Equator, 90 deg east and the poles land on the semi-axes, plus the height."""
+    for h in (0.0, 1234.5, -80.0):
+        x = oracle.ecef_wgs84([0.0, 0.0, math.pi / 2, -math.pi / 2], [0.0, math.pi / 2, 0.3, -1.1], h)
+        assert np.allclose(x[0], [WGS_A + h, 0, 0], rtol=0, atol=1e-6)
+        assert np.allclose(x[1], [0, WGS_A + h, 0], rtol=0, atol=1e-6)
+        assert np.allclose(x[2], [0, 0, WGS_B + h], rtol=0, atol=1e-6)
+        assert np.allclose(x[3], [0, 0, -(WGS_B + h)], rtol=0, atol=1e-6)
+
+
+def test_p17_wgs84_surface_normal_and_height():
+    """h = 0 lies on the ellipsoid x^2/a^2 + y^2/a^2 + z^2/b^2 = 1; the surface normal there
+    (the gradient of that form) points along (cos lat cos lon, cos lat sin lon, sin lat), the
+    definition of geodetic latitude; a height h moves the point h metres along it."""
+    rng = _rng(17)
+    lat = rng.uniform(-1.5, 1.5, 200)
+    lon = rng.uniform(-math.pi, math.pi, 200)
+    x0 = oracle.ecef_wgs84(lat, lon, 0.0)
+    q = (x0[:, 0] ** 2 + x0[:, 1] ** 2) / WGS_A ** 2 + x0[:, 2] ** 2 / WGS_B ** 2
+    assert np.max(np.abs(q - 1.0)) < 1e-14
+    n = np.stack([np.cos(lat) * np.cos(lon), np.cos(lat) * np.sin(lon), np.sin(lat)], axis=1)
+    g = np.stack([x0[:, 0] / WGS_A ** 2, x0[:, 1] / WGS_A ** 2, x0[:, 2] / WGS_B ** 2], axis=1)
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    assert np.max(np.abs(g - n)) < 1e-13
+    h = rng.uniform(-400.0, 8800.0, 200)
+    xh = oracle.ecef_wgs84(lat, lon, h)
+    assert np.max(np.abs(xh - x0 - h[:, None] * n)) < 1e-7
+
+
+def test_p17_wgs84_inverse_by_iteration_recovers_the_input():
+    """An independent inverse (fixed-point iteration on latitude and height) returns the
+    geodetic coordinates the forward map started from."""
+    rng = _rng(18)
+    lat = rng.uniform(-1.55, 1.55, 300)
+    lon = rng.uniform(-math.pi, math.pi, 300)
+    h = rng.uniform(-400.0, 9000.0, 300)
+    x = oracle.ecef_wgs84(lat, lon, h)
+    e2 = WGS_F * (2 - WGS_F)
+    p = np.hypot(x[:, 0], x[:, 1])
+    lo = np.arctan2(x[:, 1], x[:, 0])
+    la = np.arctan2(x[:, 2], p * (1 - e2))
+    hh = np.zeros_like(p)
+    for _ in range(30):
+        N = WGS_A / np.sqrt(1 - e2 * np.sin(la) ** 2)
+        hh = p / np.cos(la) - N
+        la = np.arctan2(x[:, 2], p * (1 - e2 * N / (N + hh)))
+    assert np.max(np.abs(la - lat)) < 1e-12
+    assert np.max(np.abs(np.angle(np.exp(1j * (lo - lon))))) < 1e-12
+    assert np.max(np.abs(hh - h)) < 1e-6
+
+
+def test_p17_map_at_ecef_points_equals_map_at_grid_points():
+    """The ECEF-input map at the sphere's own ECEF points is the grid map."""
+    wl = configs.SMALL.with_(n_rows=5, n_cols=6, n_samples=4000, step_len=2000)
+    scn = sim.make_scenario(wl, 2)
+    la, lo = sim.points_of(scn)
+    Jg = oracle.map_points(la, lo, scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz,
+                           pairs=list(wl.pairs), radius=wl.earth_radius_m)
+    Jx = oracle.map_xyz(oracle.grid_ecef(la, lo, wl.earth_radius_m), scn.captures, scn.states, wl.step_len,
+                        wl.fs_hz, wl.fc_hz, pairs=list(wl.pairs))
+    assert np.array_equal(Jg, Jx)
