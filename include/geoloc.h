@@ -82,6 +82,11 @@ extern "C" {
 #define GEOLOC_GRID_RECT     0   /* lat[n_rows] x lon[n_cols] */
 #define GEOLOC_GRID_POINTS   1   /* lat[P], lon[P], P = n_rows * n_cols */
 
+/* earth models (grid -> ECEF, the transformation that precedes Eq. (3)) */
+#define GEOLOC_EARTH_SPHERE  0   /* radius earth_radius_m, geocentric latitude              */
+#define GEOLOC_EARTH_WGS84   1   /* WGS-84 ellipsoid (a = 6378137 m, 1/f = 298.257223563),
+                                    geodetic latitude, height along the ellipsoid normal */
+
 /* geoloc_map flags */
 #define GEOLOC_ACCUMULATE    1u  /* add into J_dev instead of overwriting it */
 
@@ -99,10 +104,10 @@ typedef struct geoloc_desc {
     int32_t grid_kind;         /* GEOLOC_GRID_RECT or GEOLOC_GRID_POINTS                  */
     int32_t _pad0;
     int64_t n_rows, n_cols;    /* grid shape; P = n_rows * n_cols (> 0)                   */
-    const double* lat;         /* RECT: [n_rows]; POINTS: [P]  (radians)                  */
+    const double* lat;         /* RECT: [n_rows]; POINTS: [P]  (radians; geodetic for WGS-84) */
     const double* lon;         /* RECT: [n_cols]; POINTS: [P]  (radians)                  */
-    double earth_radius_m;     /* sphere radius (e.g. 6371000)                            */
-    double alt_m;              /* altitude of every candidate point above the sphere      */
+    double earth_radius_m;     /* sphere radius (e.g. 6371000); unused for WGS-84         */
+    double alt_m;              /* height of every candidate point above the surface       */
     int32_t method;            /* GEOLOC_DIRECT_FP32 / GEOLOC_CAF_BF16 / GEOLOC_CAF_FP16  */
     int32_t delay_mode;        /* GEOLOC_DELAY_LINEAR / GEOLOC_DELAY_ROUND                */
     int32_t accum_mode;        /* GEOLOC_ACC_POWER / GEOLOC_ACC_MAG                       */
@@ -113,6 +118,12 @@ typedef struct geoloc_desc {
     int32_t _pad1;
     double caf_nu_lo_hz;       /* CAF: first bin centre; NaN -> fit to the footprint      */
     double caf_nu_hi_hz;       /* CAF: last bin centre;  NaN -> fit to the footprint      */
+    int32_t earth_model;       /* GEOLOC_EARTH_SPHERE (earth_radius_m) or GEOLOC_EARTH_WGS84 */
+    int32_t _pad2;
+    const double* alt_grid;    /* NULL, or the height (m) of every candidate point above the
+                                  sphere / ellipsoid, added to alt_m (a terrain model):
+                                  RECT [n_rows][n_cols], POINTS [P]; read only during
+                                  geoloc_plan(); such a plan takes no geoloc_set_grid() */
 } geoloc_desc;
 
 /* Per-map inputs. */

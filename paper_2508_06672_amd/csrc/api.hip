@@ -61,6 +61,9 @@ struct geoloc_plan_s {
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
     int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate
     std::vector<double> h_lat, h_lon;       // grid coordinates (host copy, for the tile choice)
+    std::vector<double> h_alt;              // per-point terrain height (host copy), empty if none
+    int32_t earth_model = GEOLOC_EARTH_SPHERE;
+    double* d_alt = nullptr;         // [P] per-point terrain height, or null
     int32_t kc = 1;  // steps per geometry chunk
     // device scratch
     double* d_xyz = nullptr;
@@ -149,6 +152,7 @@ int dev_alloc(geoloc_plan_t p, T** out, size_t count) {
 void release(geoloc_plan_t p) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_xyz);
+    (void)hipFree(p->d_alt);
     (void)hipFree(p->d_lat);
     (void)hipFree(p->d_lon);
     (void)hipFree(p->d_states);
@@ -243,18 +247,33 @@ int upload_states(geoloc_plan_t p, const double* host, hipStream_t s) {
     return GEOLOC_OK;
 }
 
-// Delay (samples) and Doppler (radians per sample) of one grid cell for one pair at one
-// step, in FP64 on the host (Eq. (3)-(8) on the sphere): only the tile choice uses it.
-void host_delay_doppler(const geoloc_plan_s* p, double lat, double lon, const double* si, const double* sj, double* D,
+// Delay (samples) and Doppler (radians per sample) of RECT grid cell (r, c) for one pair at
+// one step, in FP64 on the host (Eq. (3)-(8), on the plan's earth model): only the tile
+// choice uses it.
+void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const double* si, const double* sj, double* D,
                         double* th) {
-    const double c = 299792458.0, R = p->radius + p->alt, lambda = c / p->fc;
-    const double x[3] = {R * std::cos(lat) * std::cos(lon), R * std::cos(lat) * std::sin(lon), R * std::sin(lat)};
+    const double lat = p->h_lat[r], lon = p->h_lon[c];
+    const double h = p->alt + (p->h_alt.empty() ? 0.0 : p->h_alt[r * p->cols + c]);
+    const double lambda = kLightSpeed / p->fc;
+    const double cl = std::cos(lat), sl = std::sin(lat);
+    double x[3];
+    if (p->earth_model == GEOLOC_EARTH_WGS84) {
+        const double e2 = kWgs84F * (2.0 - kWgs84F), N = kWgs84A / std::sqrt(1.0 - e2 * sl * sl);
+        x[0] = (N + h) * cl * std::cos(lon);
+        x[1] = (N + h) * cl * std::sin(lon);
+        x[2] = (N * (1.0 - e2) + h) * sl;
+    } else {
+        const double R = p->radius + h;
+        x[0] = R * cl * std::cos(lon);
+        x[1] = R * cl * std::sin(lon);
+        x[2] = R * sl;
+    }
     double tau[2], f[2];
     const double* st[2] = {si, sj};
     for (int k = 0; k < 2; ++k) {
         const double dx[3] = {st[k][0] - x[0], st[k][1] - x[1], st[k][2] - x[2]};
         const double rho = std::sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-        tau[k] = rho / c;
+        tau[k] = rho / kLightSpeed;
         f[k] = -(dx[0] * st[k][3] + dx[1] * st[k][4] + dx[2] * st[k][5]) / (rho * lambda);
     }
     *D = (tau[1] - tau[0]) * p->fs;
@@ -291,7 +310,7 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
                 const int64_t r = has_r ? r0 + i - 1 : r0, c = has_c ? c0 + j - 1 : c0;
-                host_delay_doppler(p, p->h_lat[r], p->h_lon[c], si, sj, &D[i][j], &T[i][j]);
+                host_delay_doppler(p, r, c, si, sj, &D[i][j], &T[i][j]);
             }
         std::array<double, 10> g{};
         if (has_r) {
@@ -689,8 +708,11 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     if (d->step_len > (1ll << 30) || d->n_samples > (1ll << 40)) return fail(GEOLOC_EINVAL, "capture too long");
     if (!(d->fs_hz > 0) || !(d->fc_hz > 0) || !std::isfinite(d->fs_hz) || !std::isfinite(d->fc_hz))
         return fail(GEOLOC_EINVAL, "fs_hz and fc_hz must be finite and > 0");
-    if (!(d->earth_radius_m > 0) || !std::isfinite(d->earth_radius_m) || !std::isfinite(d->alt_m))
-        return fail(GEOLOC_EINVAL, "earth_radius_m must be > 0 and alt_m finite");
+    if (d->earth_model != GEOLOC_EARTH_SPHERE && d->earth_model != GEOLOC_EARTH_WGS84)
+        return fail(GEOLOC_EINVAL, "unknown earth_model %d", d->earth_model);
+    if ((d->earth_model == GEOLOC_EARTH_SPHERE && (!(d->earth_radius_m > 0) || !std::isfinite(d->earth_radius_m))) ||
+        !std::isfinite(d->alt_m))
+        return fail(GEOLOC_EINVAL, "earth_radius_m must be > 0 (sphere) and alt_m finite");
     if (d->grid_kind != GEOLOC_GRID_RECT && d->grid_kind != GEOLOC_GRID_POINTS)
         return fail(GEOLOC_EINVAL, "unknown grid_kind %d", d->grid_kind);
     if (d->n_rows <= 0 || d->n_cols <= 0) return fail(GEOLOC_EINVAL, "empty grid");
@@ -727,6 +749,10 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if (!std::isfinite(d->lat[i])) return fail(GEOLOC_EINVAL, "lat[%lld] not finite", (long long)i);
     for (int64_t i = 0; i < n_lon; ++i)
         if (!std::isfinite(d->lon[i])) return fail(GEOLOC_EINVAL, "lon[%lld] not finite", (long long)i);
+    if (d->alt_grid)
+        for (int64_t i = 0; i < P; ++i)
+            if (!std::isfinite(d->alt_grid[i]) || std::fabs(d->alt_grid[i]) > 1.0e6)
+                return fail(GEOLOC_EINVAL, "alt_grid[%lld] not finite or beyond 1000 km", (long long)i);
     const bool caf = d->method == GEOLOC_CAF_BF16 || d->method == GEOLOC_CAF_FP16;
     if (caf) {
         if (d->caf_bins != 0 && (d->caf_bins < 4 || d->caf_bins > 65536))
@@ -770,6 +796,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     p->caf_nu_hi_req = d->caf_nu_hi_hz;
     p->radius = d->earth_radius_m;
     p->alt = d->alt_m;
+    p->earth_model = d->earth_model;
+    if (d->alt_grid) p->h_alt.assign(d->alt_grid, d->alt_grid + P);
     {
         PointTiling t{};
         if (d->grid_kind == GEOLOC_GRID_RECT) {
@@ -861,13 +889,16 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         // grid -> ECEF on the device, once per plan (and again on geoloc_set_grid)
         if ((rc = dev_alloc(p, &p->d_lat, (size_t)n_lat))) break;
         if ((rc = dev_alloc(p, &p->d_lon, (size_t)n_lon))) break;
+        if (d->alt_grid && (rc = dev_alloc(p, &p->d_alt, (size_t)P))) break;
         hipError_t e = hipMemcpy(p->d_lat, d->lat, n_lat * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess && d->alt_grid)
+            e = hipMemcpy(p->d_alt, d->alt_grid, P * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->d_lon, d->lon, n_lon * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_grid_ecef(p->d_lat, p->d_lon, d->grid_kind, d->n_rows, d->n_cols,
-                                 d->earth_radius_m + d->alt_m, p->d_xyz, nullptr);
+            e = launch_grid_ecef(p->d_lat, p->d_lon, d->grid_kind, d->n_rows, d->n_cols, p->earth_model, p->radius,
+                                 p->alt, p->d_alt, p->d_xyz, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             rc = fail(GEOLOC_ELAUNCH, "plan set-up: %s", hipGetErrorString(e));
@@ -885,6 +916,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
 int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
     if (!lat || !lon) return fail(GEOLOC_EINVAL, "NULL lat or lon");
+    if (p->d_alt) return fail(GEOLOC_EINVAL, "the plan has a height per point: make a new plan for a new grid");
     const int64_t n_lat = p->grid_kind == GEOLOC_GRID_RECT ? p->rows : p->P;
     const int64_t n_lon = p->grid_kind == GEOLOC_GRID_RECT ? p->cols : p->P;
     for (int64_t i = 0; i < n_lat; ++i)
@@ -896,7 +928,8 @@ int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     p->h_lon.assign(lon, lon + n_lon);
     HIP_TRY(hipMemcpy(p->d_lat, lat, n_lat * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_lon, lon, n_lon * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->radius + p->alt, p->d_xyz, nullptr));
+    HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->earth_model, p->radius, p->alt,
+                             nullptr, p->d_xyz, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return GEOLOC_OK;
 }

@@ -12,6 +12,8 @@
 namespace geoloc {
 
 constexpr double kLightSpeed = 299792458.0;
+constexpr double kWgs84A = 6378137.0;             // WGS-84 semi-major axis (m)
+constexpr double kWgs84F = 1.0 / 298.257223563;   // WGS-84 flattening
 
 // Points handled by one workgroup of the correlation kernels: a tile of 256 (or, for the
 // factored kernel, 512) cells of a RECT grid (neighbouring cells have neighbouring delays,
@@ -224,7 +226,8 @@ struct CafInterpArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
-                            double radius, double* xyz, hipStream_t s);
+                            int32_t model, double radius, double alt, const double* alt_p, double* xyz,
+                            hipStream_t s);
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s);
 hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s);
 // with item groups, adds the [n_groups][P] partial sums into J (onto J when load_J)

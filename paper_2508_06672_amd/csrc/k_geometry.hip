@@ -14,8 +14,14 @@ namespace geoloc {
 
 #pragma clang fp contract(off)
 
+// Candidate point -> ECEF (m). Sphere: radius (+ altitude) times the unit vector of the
+// geocentric latitude / longitude. WGS-84: geodetic latitude / longitude and a height above
+// the ellipsoid along its normal, with the prime-vertical radius N = a / sqrt(1 - e^2
+// sin^2 lat): x = (N + h) cos lat cos lon, y = (N + h) cos lat sin lon, z = (N (1 - e^2) +
+// h) sin lat. The height is alt (uniform) plus alt_p[p] when a per-point terrain is given.
 __global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ lat, const double* __restrict__ lon,
-                                                   int32_t grid_kind, int64_t rows, int64_t cols, double radius,
+                                                   int32_t grid_kind, int64_t rows, int64_t cols, int32_t model,
+                                                   double radius, double alt, const double* __restrict__ alt_p,
                                                    double* __restrict__ xyz) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= rows * cols) return;
@@ -28,10 +34,20 @@ __global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ la
         la = lat[p];
         lo = lon[p];
     }
-    double cl = cos(la);
-    xyz[3 * p + 0] = radius * cl * cos(lo);
-    xyz[3 * p + 1] = radius * cl * sin(lo);
-    xyz[3 * p + 2] = radius * sin(la);
+    const double h = alt + (alt_p ? alt_p[p] : 0.0);
+    const double cl = cos(la), sl = sin(la);
+    if (model == GEOLOC_EARTH_WGS84) {
+        const double a = kWgs84A, e2 = kWgs84F * (2.0 - kWgs84F);
+        const double N = a / sqrt(1.0 - e2 * sl * sl);
+        xyz[3 * p + 0] = (N + h) * cl * cos(lo);
+        xyz[3 * p + 1] = (N + h) * cl * sin(lo);
+        xyz[3 * p + 2] = (N * (1.0 - e2) + h) * sl;
+    } else {
+        const double R = radius + h;
+        xyz[3 * p + 0] = R * cl * cos(lo);
+        xyz[3 * p + 1] = R * cl * sin(lo);
+        xyz[3 * p + 2] = R * sl;
+    }
 }
 
 // One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
@@ -68,10 +84,12 @@ __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
 }
 
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
-                            double radius, double* xyz, hipStream_t s) {
+                            int32_t model, double radius, double alt, const double* alt_p, double* xyz,
+                            hipStream_t s) {
     int64_t P = rows * cols;
     dim3 grid((unsigned)((P + 255) / 256));
-    hipLaunchKernelGGL(k_grid_ecef, grid, dim3(256), 0, s, lat, lon, grid_kind, rows, cols, radius, xyz);
+    hipLaunchKernelGGL(k_grid_ecef, grid, dim3(256), 0, s, lat, lon, grid_kind, rows, cols, model, radius, alt, alt_p,
+                       xyz);
     return hipGetLastError();
 }
 

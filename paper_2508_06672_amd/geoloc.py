@@ -24,6 +24,7 @@ DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
 DELAY_LINEAR, DELAY_ROUND, DELAY_SINC = 0, 1, 2
 ACC_POWER, ACC_MAG = 0, 1
 GRID_RECT, GRID_POINTS = 0, 1
+EARTH_SPHERE, EARTH_WGS84 = 0, 1
 ACCUMULATE = 1
 
 
@@ -49,6 +50,7 @@ class geoloc_desc(ctypes.Structure):
         ("caf_lags", ctypes.c_int32), ("caf_bins", ctypes.c_int32),
         ("caf_lag_lo_set", ctypes.c_int32), ("caf_lag_lo", ctypes.c_int32), ("_pad1", ctypes.c_int32),
         ("caf_nu_lo_hz", ctypes.c_double), ("caf_nu_hi_hz", ctypes.c_double),
+        ("earth_model", ctypes.c_int32), ("_pad2", ctypes.c_int32), ("alt_grid", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -268,7 +270,8 @@ class Plan:
                  pairs: Optional[Sequence[Tuple[int, int]]] = None, earth_radius_m: float = 6371.0e3,
                  alt_m: float = 0.0, method: int = DIRECT_FP32, delay_mode: int = DELAY_LINEAR,
                  accum_mode: int = ACC_POWER, caf_lags: int = 0, caf_bins: int = 0,
-                 caf_lag_lo: Optional[int] = None, caf_nu_lo_hz: float = math.nan, caf_nu_hi_hz: float = math.nan):
+                 caf_lag_lo: Optional[int] = None, caf_nu_lo_hz: float = math.nan, caf_nu_hi_hz: float = math.nan,
+                 earth_model: int = EARTH_SPHERE, alt_grid=None):
         self._lat = np.ascontiguousarray(lat, dtype=np.float64).ravel()
         self._lon = np.ascontiguousarray(lon, dtype=np.float64).ravel()
         if grid_kind == GRID_RECT:
@@ -292,6 +295,13 @@ class Plan:
         d.caf_lag_lo_set = 0 if caf_lag_lo is None else 1
         d.caf_lag_lo = 0 if caf_lag_lo is None else int(caf_lag_lo)
         d.caf_nu_lo_hz, d.caf_nu_hi_hz = caf_nu_lo_hz, caf_nu_hi_hz
+        d.earth_model = earth_model
+        self._alt = None
+        if alt_grid is not None:
+            self._alt = np.ascontiguousarray(alt_grid, dtype=np.float64).ravel()
+            if self._alt.size != n_rows * n_cols:
+                raise ValueError(f"alt_grid has {self._alt.size} entries for {n_rows * n_cols} points")
+            d.alt_grid = self._alt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.n_rx, self.n_samples, self.step_len = n_rx, n_samples, step_len
         self.n_steps = n_samples // step_len
         self.n_rows, self.n_cols = n_rows, n_cols

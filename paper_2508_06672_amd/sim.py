@@ -51,6 +51,7 @@ class Emitter:
     bw_hz: float = 0.0          # chirp / sawtooth sweep (0: the workload's)
     period_s: float = 0.0       # chirp / sawtooth period (0: the workload's)
     code_seed: int = 0          # bpsk: seed of its spreading and data bits
+    ecef: Optional[Tuple[float, float, float]] = None   # position (m); None: on the sphere at (lat, lon)
 
 
 @dataclass
@@ -279,7 +280,7 @@ def make_scenario(wl: Workload, seed: int, snr_db: Optional[float] = None, noise
 
     y = np.zeros((wl.n_rx, N), dtype=np.complex128)
     for e, em in enumerate(emitters):
-        pe = _surface(em.lat, em.lon, wl.earth_radius_m)
+        pe = np.asarray(em.ecef, dtype=np.float64) if em.ecef is not None else _surface(em.lat, em.lon, wl.earth_radius_m)
         taus = [np.linalg.norm(st[:, i, 0:3] - pe, axis=1) / C_LIGHT for i in range(wl.n_rx)]
         gauss = None
         if "gauss" in em.waveform:
