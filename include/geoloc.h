@@ -175,6 +175,17 @@ int geoloc_plan(const geoloc_desc* desc, geoloc_plan_t* out_plan);
  * Errors: EINVAL (NULL or non-finite coordinates), ELAUNCH. */
 int geoloc_set_grid(geoloc_plan_t plan, const double* lat, const double* lon);
 
+/* Fix the tiling of the tile-factored kernel for the maps that follow (RECT grids, method
+ * GEOLOC_DIRECT_FP32), instead of the per-map choice from the geometry: tiles of tile_h rows
+ * of tile_w cells (tile_w x tile_h = 256, or 512 for two cells per thread; SINC 256 only),
+ * row i starting floor(shear * i / 256) columns further along, |shear| <= 1024, rows and
+ * columns swapped if transpose. tile_w = 0 returns to the per-map choice. The map is the
+ * same function of the inputs whatever the tiling (to FP32 rounding); only its speed and
+ * which tile-steps go to the per-point kernel change (with a fixed tiling, tile-steps that
+ * need more than four Taylor terms go there too). Errors: EINVAL (bad shape, shear or grid
+ * kind / method). */
+int geoloc_set_tiling(geoloc_plan_t plan, int32_t tile_w, int32_t tile_h, int32_t shear, int32_t transpose);
+
 /* Enable (nonzero) or disable per-kernel HIP-event timing of subsequent maps; either
  * way the accumulated times in geoloc_info are reset. Events are recorded on the map's
  * stream around each kernel launch, so the times are those of the kernels alone. */

@@ -60,6 +60,8 @@ struct geoloc_plan_s {
     std::vector<PointTiling> tile_shapes;   // RECT: candidate tilings of the factored kernel
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
     int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate
+    bool tiling_fixed = false;       // geoloc_set_tiling: use fixed_tiling instead of the per-map choice
+    PointTiling fixed_tiling{};
     std::vector<double> h_lat, h_lon;       // grid coordinates (host copy, for the tile choice)
     std::vector<double> h_alt;              // per-point terrain height (host copy), empty if none
     int32_t earth_model = GEOLOC_EARTH_SPHERE;
@@ -934,6 +936,34 @@ int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     return GEOLOC_OK;
 }
 
+int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t shear, int32_t transpose) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (tile_w == 0) {
+        p->tiling_fixed = false;
+        return GEOLOC_OK;
+    }
+    if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32)
+        return fail(GEOLOC_EINVAL, "a fixed tiling needs a RECT grid and GEOLOC_DIRECT_FP32");
+    const int64_t cells = (int64_t)tile_w * tile_h;
+    if (tile_w < 1 || tile_h < 1 || (cells != 256 && cells != 512))
+        return fail(GEOLOC_EINVAL, "tile must hold 256 or 512 cells (got %d x %d)", tile_w, tile_h);
+    if (cells != kTilePoints && p->delay_mode == GEOLOC_DELAY_SINC)
+        return fail(GEOLOC_EINVAL, "SINC takes 256-cell tiles");
+    if (shear < -kMaxShear || shear > kMaxShear) return fail(GEOLOC_EINVAL, "|shear| must be <= %d", kMaxShear);
+    if (transpose != 0 && transpose != 1) return fail(GEOLOC_EINVAL, "transpose must be 0 or 1");
+    PointTiling t = p->base_tiling;
+    t.tile_w = tile_w;
+    t.tile_h = tile_h;
+    t.shear = shear;
+    t.transpose = transpose;
+    tiling_counts(t);
+    if (t.tiles_x * t.tiles_y > p->max_tiles || t.tiles_x * t.tiles_y * cells > p->max_table)
+        return fail(GEOLOC_EINVAL, "tiling exceeds the plan's scratch");
+    p->fixed_tiling = t;
+    p->tiling_fixed = true;
+    return GEOLOC_OK;
+}
+
 int geoloc_set_timing(geoloc_plan_t p, int enable) {
     if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
     int rc = drain_spans(p);
@@ -952,7 +982,12 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
     hipStream_t s = (hipStream_t)in->stream;
     int rc = upload_states(p, in->rx_state, s);
     if (rc) return rc;
-    choose_tiling(p, in->rx_state);
+    if (p->tiling_fixed) {
+        p->tiling = p->fixed_tiling;
+        p->fact_wide = false;   // tile-steps that need more than four Taylor terms are deferred
+    } else {
+        choose_tiling(p, in->rx_state);
+    }
     TimedSpan whole{};
     if ((rc = span_begin(p, s, &whole, 3))) return rc;
     if (p->method == GEOLOC_CAF_BF16 || p->method == GEOLOC_CAF_FP16) {

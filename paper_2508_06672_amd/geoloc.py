@@ -102,6 +102,7 @@ def load() -> ctypes.CDLL:
     lib.geoloc_detect.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_int32), _vp]
+    lib.geoloc_set_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
     lib.geoloc_destroy.argtypes = [_vp]
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
@@ -109,7 +110,7 @@ def load() -> ctypes.CDLL:
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
-                 "geoloc_detect", "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
+                 "geoloc_detect", "geoloc_set_tiling", "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -365,6 +366,11 @@ class Plan:
 
     def argmax(self, J, top_k: int = 1, nms_radius: int = 0, stream=None):
         return geoloc_argmax(self.handle, J.data_ptr(), top_k, nms_radius, _stream_handle(stream))
+
+    def set_tiling(self, tile_w: int = 0, tile_h: int = 0, shear: int = 0, transpose: int = 0) -> None:
+        """Fix the factored kernel's tiling (shear in 1/256 column per row); tile_w = 0 returns
+        to the per-map choice."""
+        _check(load().geoloc_set_tiling(self.handle, tile_w, tile_h, shear, transpose), "geoloc_set_tiling")
 
     def detect(self, J, guard: int, train: int, scale: float, max_detections: int = 16, nms_radius: int = 0,
                stream=None):

@@ -291,3 +291,34 @@ def test_step_segments(torch, G, delay, accum, spacing):
     assert info["step_segments"] == 11 and info["segment_len"] == 4096
     assert err_J(Jg, Jo) <= DIRECT_TOL
     check_argmax(Jg, Jo, DIRECT_TOL)
+
+
+@pytest.mark.parametrize("w,h,shear,tr,spacing,delay", [(16, 32, 0, 0, 8000.0, 0), (8, 64, 333, 1, 500.0, 0),
+                                                        (4, 128, -700, 0, 500.0, 1), (32, 16, 150, 1, 8000.0, 1),
+                                                        (4, 64, -100, 0, 500.0, 2), (16, 16, 1024, 1, 2000.0, 2)])
+def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
+    """Tilings the plan would not pick, fixed through geoloc_set_tiling: 512-cell tiles on 8 km
+    cells (most tile-steps deferred to the per-point kernel in two 256-lane halves), steep
+    and fractional shears, both orientations, SINC on 256-cell tiles; all match the oracle.
+    Returning to the per-map choice works, and bad tilings are rejected."""
+    wl = configs.MAP_1E6.with_(n_rows=45, n_cols=52, spacing_m=spacing, n_samples=30_000)
+    scn = sim.make_scenario(wl, 60 + w + h + delay)
+    log(f"fixed tiling {w}x{h} shear {shear} transpose {tr} spacing {spacing} delay {delay}")
+    Jo = oracle.map_scenario(scn, delay_mode=delay)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn, delay_mode=delay) as plan:
+        plan.set_tiling(w, h, shear, tr)
+        plan.set_timing(True)
+        Jg = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        info = plan.info()
+        assert (info["tile_cols"], info["tile_rows"], info["tile_shear"], info["tile_transpose"]) == (w, h, shear, tr)
+        log(f"  err_J = {err_J(Jg, Jo):.3g}, per-point pass {info['interp_ms']:.3f} ms")
+        assert err_J(Jg, Jo) <= DIRECT_TOL
+        check_argmax(Jg, Jo, DIRECT_TOL)
+        plan.set_tiling(0)
+        J2 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        assert err_J(J2, Jo) <= DIRECT_TOL
+        for bad in [(10, 10, 0, 0), (16, 16, 1025, 0), (16, 16, 0, 2)] + ([(16, 32, 0, 0)] if delay == 2 else []):
+            with pytest.raises(G.GeolocError) as ei:
+                plan.set_tiling(*bad)
+            assert ei.value.status == G.EINVAL, bad
