@@ -291,7 +291,7 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // and the per-point combination about (4Q + 6) / 64 (LINEAR; fewer for ROUND, more for
 // SINC); a tile that the factored kernel would defer costs about 13. A tiling whose launch
 // has fewer than 768 workgroups (three per CU) is charged for the idle share of the chip,
-// and SINC, bound by its per-point work and registers, keeps to 256-cell tiles. Taylor orders 5 and 6 need the kernel's
+// and SINC keeps to 256-cell tiles at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
 // are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
 void choose_tiling(geoloc_plan_t p, const double* states) {
@@ -356,6 +356,7 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         return p->delay_mode == GEOLOC_DELAY_SINC ? 18.0 * Q + 6.0
                                                   : (p->delay_mode == GEOLOC_DELAY_ROUND ? 2.0 : 4.0) * Q + 6.0;
     };
+    const double taps = p->delay_mode == GEOLOC_DELAY_SINC ? 8.0 : 2.0;   // lags each cell reads
     auto cost = [&](const PointTiling& t, int* q_need) {
         double total = 0.0;
         *q_need = 0;
@@ -376,7 +377,7 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         for (size_t gi = 0; gi < grads.size(); ++gi) {
             const auto& g = grads[gi];
             const bool tr = t.transpose != 0;
-            const double H = spread(tr ? g[1] : g[0], tr ? g[0] : g[1], tr ? g[5] : g[4], tr ? g[4] : g[5], g[6]) + 3.0;
+            const double H = spread(tr ? g[1] : g[0], tr ? g[0] : g[1], tr ? g[5] : g[4], tr ? g[4] : g[5], g[6]) + taps + 1.0;
             const double xr = 0.5 * spread(tr ? g[3] : g[2], tr ? g[2] : g[3], tr ? g[8] : g[7], tr ? g[7] : g[8], g[9]) *
                               (0.5 * 64.0);
             int Q = 0;
@@ -403,8 +404,10 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     int q_best = 0, q = 0;
     double best = cost(p->base_tiling, &q_best);
     for (const auto& shape : p->tile_shapes) {
-        // the SINC combination is bound by per-point work and registers: 256-cell tiles only
-        if (p->delay_mode == GEOLOC_DELAY_SINC && tile_lanes(shape) != kTilePoints) continue;
+        // the SINC combination is bound by per-point work, registers and LDS reads: 256-cell
+        // tiles at most 8 cells wide (on the 1e6-point map 16-wide tiles ran 1.4x slower,
+        // each wave's cells reading twice as many distinct lags per block)
+        if (p->delay_mode == GEOLOC_DELAY_SINC && (tile_lanes(shape) != kTilePoints || shape.tile_w > 8)) continue;
         // shears: whole columns per row, and the slope of each pair's lines of equal delay
         std::vector<int32_t> shears = {-2 * kShearOne, -kShearOne, 0, kShearOne, 2 * kShearOne};
         for (const auto& g : grads) {
