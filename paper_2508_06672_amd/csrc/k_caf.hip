@@ -145,6 +145,12 @@ struct MfmaTypes<false> {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
     static __device__ inline unsigned short cvt(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+    // two values rounded to nearest even and packed, low half first (one conversion instruction)
+    static __device__ inline unsigned int cvt2(float lo, float hi) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2){lo, hi}, b2));
+    }
 };
 template <>
 struct MfmaTypes<true> {
@@ -153,6 +159,11 @@ struct MfmaTypes<true> {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
     }
     static __device__ inline unsigned short cvt(float x) { return __builtin_bit_cast(unsigned short, (_Float16)x); }
+    static __device__ inline unsigned int cvt2(float lo, float hi) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(unsigned int, __builtin_convertvector((f2){lo, hi}, h2));
+    }
 };
 
 template <bool kF16>
@@ -226,19 +237,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEOLOC_CAF_
                 u32x4 par, pai;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    unsigned int wr = 0, wi = 0;
+                    float lr[2], li[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const int t = ks * 16 + kg * 8 + 2 * q + h;
                         const float2 x = s_yi[t];
                         const float2 y = s_yj[t + row];
-                        const float lr = fmaf(x.x, y.x, x.y * y.y);  // x * conj(y)
-                        const float li = fmaf(x.y, y.x, -(x.x * y.y));
-                        wr |= (unsigned int)MT::cvt(lr) << (16 * h);
-                        wi |= (unsigned int)MT::cvt(li) << (16 * h);
+                        lr[h] = fmaf(x.x, y.x, x.y * y.y);  // x * conj(y)
+                        li[h] = fmaf(x.y, y.x, -(x.x * y.y));
                     }
-                    par[q] = wr;
-                    pai[q] = wi;
+                    par[q] = MT::cvt2(lr[0], lr[1]);
+                    pai[q] = MT::cvt2(li[0], li[1]);
                 }
                 const u32x4 pnai = pai ^ 0x80008000u;   // -Ai: flip both sign bits of each word
                 const vec va = __builtin_bit_cast(vec, par);
