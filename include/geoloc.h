@@ -54,9 +54,10 @@ extern "C" {
 
 /* method */
 #define GEOLOC_DIRECT_FP32   0   /* Eq. (11) in FP32 with FP64 geometry; the per-point sums
-                                    are factored through lag moments shared by a tile of 256
-                                    points (16 x 16 cells on RECT grids, 256 consecutive
-                                    points on POINTS grids), with a Taylor remainder of at
+                                    are factored through lag moments shared by a tile of
+                                    points (256 or 512 cells of a RECT grid in a slanted tile
+                                    chosen per map, 256 consecutive points of a POINTS
+                                    list), with a Taylor remainder of at
                                     most 2^-24 of each 64-sample block's magnitude sum;
                                     tiles whose lags or Doppler shifts spread too widely are
                                     summed point by point */

@@ -56,7 +56,7 @@ struct geoloc_plan_s {
     double fs = 0, fc = 0, radius = 0, alt = 0;
     std::vector<int2> pairs;
     PointTiling tiling{};            // tiling of the current map
-    PointTiling base_tiling{};       // 16 x 16 squares (RECT) or runs of 256 points (POINTS)
+    PointTiling base_tiling{};       // 16 x 16 squares (RECT; CAF and per-point paths) or runs of 256 points (POINTS)
     std::vector<PointTiling> tile_shapes;   // RECT: candidate tilings of the factored kernel
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
     int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate

@@ -8,7 +8,7 @@
 //   J(p) += |C|^2  (or |C|).
 //
 // Mapping on gfx950 (64-wide wavefronts, 160 KiB LDS per CU):
-//  * one workgroup = 256 candidate points (a 16 x 16 cell tile of a rectilinear grid),
+//  * one workgroup = 256 candidate points (a tile of a rectilinear grid, or one half of a 512-cell tile),
 //    one point per lane; a point owns its J value for the whole launch, so the sums
 //    over steps and pairs need no atomics and are deterministic;
 //  * the FP64 geometry table is stored tile-major, so each workgroup reads one aligned,

@@ -1,10 +1,11 @@
 // k_direct_fact.hip -- direct position-domain correlation (Sec. III, Eq. (11)) with the
 // per-point work factored through lag moments shared by a tile of points.
 //
-// Within a 16 x 16 tile of candidate points the delays and Doppler shifts of one step are
-// close. Split the step into blocks of B = 64 samples (block centre c_b, sample offset
-// r = n - c_b in [-31.5, 31.5]) and write each point's rotation rate as the tile's mean
-// plus a small deviation, theta_p = theta_bar + delta_p (radians per sample). Then
+// Within a tile of 256 or 512 candidate points (a slanted parallelogram that follows the
+// lines of equal delay) the delays and Doppler shifts of one step are close. Split the step
+// into blocks of B = 64 samples (block centre c_b, sample offset r = n - c_b in [-31.5,
+// 31.5]) and write each point's rotation rate as the tile's mean plus a small deviation,
+// theta_p = theta_bar + delta_p (radians per sample). Then
 //
 //   C_p = sum_b W_b(p) sum_r x[n] e^{j theta_bar r} e^{j delta_p r} conj(yt_p[n]),
 //   W_b(p) = exp(j theta_p (c_b - c)),
@@ -15,18 +16,18 @@
 //   a_q(p) = (j delta_p)^q / q!,   G_q(b, d) = sum_{r in b} r^q x[n] e^{j theta_bar r} conj(y_j[n + d]).
 //
 // The moments G_q(b, d) depend on the lag only, not on the point, so a tile computes them
-// once for its few dozen lags and every point combines 2Q of them per block: about 2 VALU
-// instructions per grid-point x sample correlation instead of 13 for the per-point form.
-// The moment work is spread over the workgroup as (block, lag pair) items, floor(256 /
-// ceil(H / 2)) blocks per round, so that few lanes idle whatever the tile's lag spread H;
-// the two lags of a lane share every sample read but one, which halves the LDS reads.
-// Each block's reference samples sit 66 words apart in LDS, so that the blocks that share
-// a wave read different banks. The step body is compiled per Taylor order. Q is chosen
-// per tile and step so that the Taylor remainder bound is at most one FP32 unit roundoff
-// (2^-24) of the block's magnitude sum, below the rounding of the block sum itself; a tile
-// whose lag spread exceeds kFH or whose Doppler spread needs more Taylor terms than the
-// variant carries (4, or 6 in the variant the host picks for wide Doppler spreads) is flagged
-// in `deferred` and left to the per-point kernel, which then adds that step into J.
+// once for its dozen or so lags and every point combines 2Q of them per block (ROUND: Q;
+// the eight-tap SINC delay: 8Q) by Horner's rule over the blocks. The moment work is
+// spread over the workgroup as (block, lag pair) items, floor(256 / ceil(H / 2)) blocks
+// per round, so that few lanes idle whatever the tile's lag spread H; the two lags of a
+// lane share every sample read but one, which halves the LDS reads. Each block's
+// reference samples sit 66 words apart in LDS, so that the blocks that share a wave read
+// different banks. The step body is compiled per Taylor order. Q is chosen per tile and
+// step so that the Taylor remainder bound is at most one FP32 unit roundoff (2^-24) of the
+// block's magnitude sum, below the rounding of the block sum itself; a tile whose lag
+// spread exceeds kFH or whose Doppler spread needs more Taylor terms than the variant
+// carries (4, or 6 in the variant the host picks for wide Doppler spreads) is flagged in
+// `deferred` and left to the per-point kernel, which then adds that step into J.
 #include "internal.h"
 
 #include <cfloat>

@@ -2,7 +2,7 @@
 // (GEOLOC_DELAY_SINC): the kernel of GEOLOC_DIRECT_FP32_POINTWISE in that mode, and the
 // pass over the (tile, step) pairs the factored kernel defers.
 //
-// One lane per point, one workgroup per tile of 256 points and group of (pair, step)
+// One lane per point, one workgroup per 256 points of a tile and group of (pair, step)
 // items, as in the other correlation kernels (same tiling, masks and partial rows). Per
 // sample a lane reads y_i[n] (the same address for every lane: one broadcast load) and the
 // eight taps y_j[n + floor(D) - 3 .. n + floor(D) + 4] from global memory; the taps slide in
