@@ -322,3 +322,27 @@ def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
             with pytest.raises(G.GeolocError) as ei:
                 plan.set_tiling(*bad)
             assert ei.value.status == G.EINVAL, bad
+
+
+def test_random_tilings_on_ragged_grids(torch, G):
+    """Twenty seeded random tilings (shape, shear in 1/256 column per row, orientation) on
+    grids of odd sizes, some narrower than a tile: every cell is covered exactly once and
+    the map matches the oracle."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    shapes = [(16, 16), (8, 32), (4, 64), (32, 8), (64, 4), (16, 32), (8, 64), (4, 128), (32, 16), (128, 4)]
+    wl0 = configs.MAP_1E6.with_(n_samples=20_000, step_len=10_000)
+    for case in range(20):
+        rows, cols = int(rng.integers(3, 70)), int(rng.integers(3, 70))
+        w, h = shapes[int(rng.integers(len(shapes)))]
+        shear = int(rng.integers(-1024, 1025))
+        tr = int(rng.integers(2))
+        wl = wl0.with_(n_rows=rows, n_cols=cols, spacing_m=float(rng.choice([500.0, 2000.0])))
+        scn = sim.make_scenario(wl, 500 + case)
+        Jo = oracle.map_scenario(scn)
+        caps = torch.from_numpy(scn.captures).cuda()
+        with G.Plan.for_scenario(scn) as plan:
+            plan.set_tiling(w, h, shear, tr)
+            Jg = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        e = err_J(Jg, Jo)
+        log(f"  case {case}: {rows}x{cols} tile {w}x{h} shear {shear} transpose {tr}: err_J {e:.3g}")
+        assert e <= DIRECT_TOL, (case, rows, cols, w, h, shear, tr)
