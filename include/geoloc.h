@@ -176,6 +176,18 @@ int geoloc_plan(const geoloc_desc* desc, geoloc_plan_t* out_plan);
  * Errors: EINVAL (NULL or non-finite coordinates), ELAUNCH. */
 int geoloc_set_grid(geoloc_plan_t plan, const double* lat, const double* lon);
 
+/* Make a POINTS plan's points the cells of whole tiles of a rectilinear grid, tile by tile,
+ * without a host round trip: lat_dev[rows] / lon_dev[cols] are DEVICE arrays (radians) of
+ * the full grid, tile the tile side in cells (rows and cols multiples of it), tiles[n_tiles]
+ * a HOST array of tile indices (tile row x cols / tile + tile column), and n_tiles x tile^2
+ * must equal the plan's point count. Point p is cell w = p % tile^2 (row-major within the
+ * tile) of tile tiles[p / tile^2]; a tile index outside the grid gives NaN points. Runs
+ * asynchronously on `stream` (the grid -> ECEF conversion included); the next map on that
+ * stream sees the new points. For the refinement of a tile proposal. Errors: EINVAL (not a
+ * POINTS plan, a plan with per-point heights, bad sizes), ENOMEM, ELAUNCH. */
+int geoloc_set_points_from_tiles(geoloc_plan_t plan, const double* lat_dev, const double* lon_dev, int64_t rows,
+                                 int64_t cols, int32_t tile, const int32_t* tiles, int32_t n_tiles, void* stream);
+
 /* Fix the tiling of the tile-factored kernel for the maps that follow (RECT grids, method
  * GEOLOC_DIRECT_FP32), instead of the per-map choice from the geometry: tiles of tile_h rows
  * of tile_w cells (tile_w x tile_h = 256, or 512 for two cells per thread; SINC 256 only),

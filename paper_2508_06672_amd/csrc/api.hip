@@ -61,6 +61,8 @@ struct geoloc_plan_s {
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
     int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate
     bool tiling_fixed = false;       // geoloc_set_tiling: use fixed_tiling instead of the per-map choice
+    int32_t* d_tiles = nullptr;      // geoloc_set_points_from_tiles: the tile list
+    int32_t d_tiles_cap = 0;
     PointTiling fixed_tiling{};
     std::vector<double> h_lat, h_lon;       // grid coordinates (host copy, for the tile choice)
     std::vector<double> h_alt;              // per-point terrain height (host copy), empty if none
@@ -155,6 +157,7 @@ void release(geoloc_plan_t p) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_xyz);
     (void)hipFree(p->d_alt);
+    (void)hipFree(p->d_tiles);
     (void)hipFree(p->d_lat);
     (void)hipFree(p->d_lon);
     (void)hipFree(p->d_states);
@@ -936,6 +939,35 @@ int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->earth_model, p->radius, p->alt,
                              nullptr, p->d_xyz, nullptr));
     HIP_TRY(hipDeviceSynchronize());
+    return GEOLOC_OK;
+}
+
+int geoloc_set_points_from_tiles(geoloc_plan_t p, const double* lat_dev, const double* lon_dev, int64_t rows,
+                                 int64_t cols, int32_t tile, const int32_t* tiles, int32_t n_tiles, void* stream) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (!lat_dev || !lon_dev || !tiles) return fail(GEOLOC_EINVAL, "NULL pointer");
+    if (p->grid_kind != GEOLOC_GRID_POINTS) return fail(GEOLOC_EINVAL, "needs a POINTS plan");
+    if (p->d_alt) return fail(GEOLOC_EINVAL, "the plan has a height per point: make a new plan for a new grid");
+    if (tile < 1 || rows < tile || cols < tile || rows % tile || cols % tile)
+        return fail(GEOLOC_EINVAL, "rows and cols must be positive multiples of tile");
+    if (n_tiles < 1 || (int64_t)n_tiles * tile * tile != p->P)
+        return fail(GEOLOC_EINVAL, "n_tiles x tile^2 must equal the plan's %lld points", (long long)p->P);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->d_tiles_cap < n_tiles) {
+        (void)hipFree(p->d_tiles);
+        p->d_tiles = nullptr;
+        p->d_tiles_cap = 0;
+        int rc = dev_alloc(p, &p->d_tiles, (size_t)n_tiles);
+        if (rc) return rc;
+        p->d_tiles_cap = n_tiles;
+    }
+    HIP_TRY(hipMemcpyAsync(p->d_tiles, tiles, (size_t)n_tiles * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_tile_points(lat_dev, lon_dev, rows, cols, tile, p->d_tiles, p->P, p->d_lat, p->d_lon, s));
+    HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->earth_model, p->radius, p->alt,
+                             nullptr, p->d_xyz, s));
+    // the host copy of the grid serves the tile choice of RECT plans only
+    p->h_lat.clear();
+    p->h_lon.clear();
     return GEOLOC_OK;
 }
 

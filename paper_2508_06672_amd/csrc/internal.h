@@ -229,6 +229,8 @@ hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_k
                             int32_t model, double radius, double alt, const double* alt_p, double* xyz,
                             hipStream_t s);
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s);
+hipError_t launch_tile_points(const double* glat, const double* glon, int64_t rows, int64_t cols, int32_t tile,
+                              const int32_t* tiles, int64_t P, double* lat, double* lon, hipStream_t s);
 hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s);
 // with item groups, adds the [n_groups][P] partial sums into J (onto J when load_J)
 hipError_t launch_direct_reduce(const DirectArgs& a, hipStream_t s);

@@ -50,6 +50,35 @@ __global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ la
     }
 }
 
+// Points of whole tiles of a rectilinear grid, tile by tile (a POINTS plan's grid): point p
+// is cell (tile_row * tile + w / tile, tile_col * tile + w % tile) of tile tiles[p / tile^2],
+// w = p % tile^2, with tile index tile_row * (cols / tile) + tile_col. An index outside the
+// grid gives NaN coordinates (and a NaN map there) instead of a read out of bounds.
+__global__ __launch_bounds__(256) void k_tile_points(const double* __restrict__ glat, const double* __restrict__ glon,
+                                                     int64_t rows, int64_t cols, int32_t tile,
+                                                     const int32_t* __restrict__ tiles, int64_t P,
+                                                     double* __restrict__ lat, double* __restrict__ lon) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int64_t cells = (int64_t)tile * tile;
+    const int64_t t = tiles[p / cells], w = p % cells;
+    const int64_t tcols = cols / tile, n_tiles = (rows / tile) * tcols;
+    if (t < 0 || t >= n_tiles) {
+        lat[p] = lon[p] = __builtin_nan("");
+        return;
+    }
+    const int64_t r = (t / tcols) * tile + w / tile, c = (t % tcols) * tile + w % tile;
+    lat[p] = glat[r];
+    lon[p] = glon[c];
+}
+
+hipError_t launch_tile_points(const double* glat, const double* glon, int64_t rows, int64_t cols, int32_t tile,
+                              const int32_t* tiles, int64_t P, double* lat, double* lon, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_points, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, glat, glon, rows, cols, tile,
+                       tiles, P, lat, lon);
+    return hipGetLastError();
+}
+
 // One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
 // Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * lanes + lane, with the point of
 // (tile, lane) as in the correlation kernels; lanes past the grid edge write zeros.

@@ -103,6 +103,8 @@ def load() -> ctypes.CDLL:
                                   ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_int32), _vp]
     lib.geoloc_set_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.geoloc_set_points_from_tiles.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                                 P(ctypes.c_int32), ctypes.c_int32, _vp]
     lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
     lib.geoloc_destroy.argtypes = [_vp]
     lib.geoloc_strerror.argtypes = [ctypes.c_int]
@@ -110,7 +112,8 @@ def load() -> ctypes.CDLL:
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
-                 "geoloc_detect", "geoloc_set_tiling", "geoloc_info", "geoloc_destroy", "geoloc_subbands"):
+                 "geoloc_detect", "geoloc_set_tiling", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
+                 "geoloc_subbands"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -386,6 +389,16 @@ class Plan:
             raise ValueError(f"grid coordinates {(lat.size, lon.size)} != {want}")
         geoloc_set_grid(self.handle, lat, lon)
         self._lat, self._lon = lat, lon
+
+    def set_points_from_tiles(self, lat_dev, lon_dev, tile: int, tiles, stream=None) -> None:
+        """Points = the cells of whole tiles (tile index = tile row x n_cols / tile + tile column)
+        of the grid lat_dev x lon_dev (device float64 tensors), tile by tile, set on the device."""
+        t = np.ascontiguousarray(np.asarray(tiles, dtype=np.int32).ravel())
+        self._tiles = t                     # the host tile list stays alive past the copy
+        _check(load().geoloc_set_points_from_tiles(self.handle, lat_dev.data_ptr(), lon_dev.data_ptr(),
+                                                   lat_dev.numel(), lon_dev.numel(), tile,
+                                                   t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), t.size,
+                                                   _stream_handle(stream)), "geoloc_set_points_from_tiles")
 
     def set_timing(self, enable: bool = True) -> None:
         geoloc_set_timing(self.handle, enable)

@@ -153,10 +153,12 @@ class Proposer:
         self.refine = geoloc.Plan(lat=plat, lon=plon, grid_kind=geoloc.GRID_POINTS, **kw)
         self.full = geoloc.Plan(lat=lat0, lon=lon0, **kw)
         self.lat, self.lon = lat0, lon0
+        self._lat_dev = self._lon_dev = None      # the fine grid's axes on the device
         self.n_tile_rows, self.n_tile_cols = wl.n_rows // TILE, wl.n_cols // TILE
 
     def set_grid(self, lat: np.ndarray, lon: np.ndarray) -> None:
         self.lat, self.lon = np.asarray(lat), np.asarray(lon)
+        self._lat_dev = self._lon_dev = None
         self.coarse.set_grid(*coarse_axes(lat, lon))
         self.full.set_grid(lat, lon)
 
@@ -176,11 +178,20 @@ class Proposer:
         return Jc, x
 
     def refine_tiles(self, caps, states, tiles):
-        plat, plon, idx = tile_points(self.lat, self.lon, tiles)
-        self.refine.set_grid(plat, plon)
+        """Map the cells of the given tiles (set on the device from the tile list) and return
+        the best one's flat index on the fine grid and its value."""
+        import torch
+        if self._lat_dev is None:
+            self._lat_dev = torch.from_numpy(np.ascontiguousarray(self.lat, dtype=np.float64)).to(caps.device)
+            self._lon_dev = torch.from_numpy(np.ascontiguousarray(self.lon, dtype=np.float64)).to(caps.device)
+        tiles = np.asarray(tiles, dtype=np.int64)
+        self.refine.set_points_from_tiles(self._lat_dev, self._lon_dev, TILE, tiles)
         J = self.refine.map(caps, states)
         i, v = self.refine.argmax(J)
-        return int(idx[int(i[0])]), float(v[0])
+        t, w = divmod(int(i[0]), TILE * TILE)
+        R, C = divmod(int(tiles[t]), self.lon.size // TILE)
+        r, c = R * TILE + w // TILE, C * TILE + w % TILE
+        return r * self.lon.size + c, float(v[0])
 
     def full_map(self, caps, states):
         J = self.full.map(caps, states)

@@ -53,8 +53,10 @@ def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
 def test_refined_tiles_reproduce_the_full_map(torch, P):
     """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals the
     full-grid map at those cells to FP32 rounding (the full grid may use sheared tiles, so
-    the sums group differently), as does the per-point kernel. When the chosen tiles
-    contain the full map's peak the refined peak is that peak."""
+    the sums group differently), as does the per-point kernel; the same points set on the
+    device from the tile list give the same map bit for bit, a tile index outside the grid
+    gives NaN, and bad sizes are rejected. When the chosen tiles contain the full map's peak
+    the refined peak is that peak."""
     from paper_2508_06672_amd import geoloc
     wl = SMALL_WL
     net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
@@ -75,6 +77,25 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     prop.refine.set_grid(plat, plon)
     Jr = prop.refine.map(caps, states).cpu().numpy()
     assert float(np.max(np.abs(Jr.astype(np.float64) - Jf[idx]))) <= 2e-5 * float(Jf.max())
+    # the same points set on the device from the tile list give the same map, bit for bit
+    lat_d = torch.from_numpy(np.ascontiguousarray(scn.lat)).cuda()
+    lon_d = torch.from_numpy(np.ascontiguousarray(scn.lon)).cuda()
+    prop.refine.set_points_from_tiles(lat_d, lon_d, P.TILE, tiles)
+    Jd = prop.refine.map(caps, states).cpu().numpy()
+    assert np.array_equal(Jd, Jr)
+    bad = list(tiles)
+    bad[3] = (wl.n_rows // P.TILE) * (wl.n_cols // P.TILE)      # one past the last tile
+    prop.refine.set_points_from_tiles(lat_d, lon_d, P.TILE, bad)
+    with pytest.raises(geoloc.GeolocError) as ei:
+        prop.refine.argmax(prop.refine.map(caps, states))
+    assert ei.value.status == geoloc.ENAN
+    for args in [(lat_d, lon_d, P.TILE, tiles[:-1]), (lat_d, lon_d, 7, tiles)]:
+        with pytest.raises(geoloc.GeolocError) as ei:
+            prop.refine.set_points_from_tiles(*args)
+        assert ei.value.status == geoloc.EINVAL
+    with pytest.raises(geoloc.GeolocError) as ei:
+        prop.full.set_points_from_tiles(lat_d, lon_d, P.TILE, tiles)
+    assert ei.value.status == geoloc.EINVAL
     i, v = prop.refine_tiles(caps, states, tiles)
     assert Jf[i] >= (1 - 4e-5) * v_full and abs(v - v_full) <= 2e-5 * v_full
     prop.close()
