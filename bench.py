@@ -85,12 +85,16 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     """Algorithmic FP32 operations of one map in the tile-factored form, from the map's own
     geometry, with each tile (of the shape the plan chose for the map) and step classified
     as the kernel does (lag spread H = max d0 - min d0 + 2, Taylor order Q from the tile's
-    Doppler spread, deferred when H > 128 or no Q <= 4 bounds the remainder). Per factored
-    tile and step: rotation of the reference samples 6 L; lag moments H L (6 + 2 + 4 (Q - 1));
-    per point and 64-sample block 4 flops per Taylor term and lag read (two lags for LINEAR,
-    whose interpolation weights are folded into the Taylor coefficients; one for ROUND) and
-    6 for the block weight (one Horner step, a complex product by a unit phasor). Returns
-    (flops, factored units, deferred tile-steps, all tile-steps)."""
+    Doppler spread over the plan's Taylor block of B = 64 or 256 samples, deferred when
+    H > 128 or no Q <= 4 bounds the remainder). Per factored tile and step: rotation of the
+    reference samples 6 L; lag moments of the 64-sample sub-blocks H L (6 + 2 + 4 (Q - 1));
+    for B = 256, per lag and sub-block the shift to the long block's centre (Q (Q - 1) / 2
+    complex multiply-adds by a real weight, 4 flops each) and per lag and long block the sum
+    of its four sub-blocks (3 Q complex additions); per point and Taylor block 4 flops per
+    Taylor term and lag read (two lags for LINEAR, whose interpolation weights are folded
+    into the Taylor coefficients; one for ROUND) and 6 for the block weight (one Horner step,
+    a complex product by a unit phasor). Returns (flops, factored units, deferred
+    tile-steps, all tile-steps)."""
     import numpy as np
     info = plan.info()
     idx = torch.from_numpy(tile_index(wl.n_rows, wl.n_cols, info["tile_cols"], info["tile_rows"],
@@ -98,7 +102,10 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     valid = idx >= 0
     gidx = idx.clamp(min=0)
     L = wl.step_len
-    nblk = -(-L // FB)
+    TB = int(info.get("taylor_block") or FB)
+    sub = TB // FB
+    nblk = -(-L // TB)
+    nsub = -(-L // FB)
     inv_fact = [1.0 / float(np.prod(range(1, q + 1))) for q in range(1, FQ + 1)]
     flops = 0.0
     units = 0.0
@@ -121,7 +128,7 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         tlo = tiles(th, inf).amin(-1)
         thi = tiles(th, -inf).amax(-1)
         H = dhi - dlo + 2
-        xr = 0.5 * (thi - tlo) * (0.5 * FB)
+        xr = 0.5 * (thi - tlo) * (0.5 * TB)
         qs = torch.arange(1, FQ + 1, device=xr.device, dtype=torch.float32)
         terms = xr.unsqueeze(-1) ** qs * torch.tensor(inv_fact, dtype=torch.float32, device=xr.device)
         ok = (terms <= FTOL) & (xr < 1).unsqueeze(-1)
@@ -129,6 +136,8 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         fac = (Q > 0) & (H <= FH) & (nval > 0)     # tiles with no grid cell do no work
         per_point = nblk * ((4 if delay_round else 8) * Q + 6)
         f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
+        if sub > 1:
+            f = f + H * nsub * 2 * Q * (Q - 1) + H * nblk * 2 * Q * (sub - 1)
         flops += float(torch.where(fac, f, torch.zeros_like(f)).sum())
         units += float(torch.where(fac, nval * L, torch.zeros_like(f)).sum())
         deferred += int((~fac & (nval > 0)).sum())
@@ -325,7 +334,7 @@ def delay_modes_leg(geoloc, torch, scn, caps):
             info = plan.info()
         out[name] = {"map_ms": e0.elapsed_time(e1), "peak": float(val[0]), "argmax": int(idx[0]),
                      "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f}"
-                             f"{' transposed' if info['tile_transpose'] else ''}"}
+                             f"{' transposed' if info['tile_transpose'] else ''}", "taylor_block": info["taylor_block"]}
     for name in ("linear", "round"):
         out[name]["peak_vs_sinc"] = out[name]["peak"] / out["sinc"]["peak"]
     return out
@@ -463,6 +472,7 @@ def main() -> int:
                 "deferred_tile_steps": f"{n_def}/{n_ts}",
                 "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f} columns/row"
                         f"{' transposed' if info['tile_transpose'] else ''}",
+                "taylor_block": info["taylor_block"],
                 "pointwise_equivalent_tflops": round(FLOP_PER_UNIT_POINTWISE * units_per_launch / (k_ms / 1e3) / 1e12,
                                                      3)}
 

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GEOLOC_ABI_VERSION 3
+#define GEOLOC_ABI_VERSION 4
 
 /* status codes */
 #define GEOLOC_OK            0
@@ -159,6 +159,10 @@ typedef struct geoloc_plan_info {
                                   across workgroups (1 = not split); their complex partial
                                   sums are added before |C|^2 is taken                   */
     int32_t segment_len;       /* samples per segment (step_len when not split)          */
+    int32_t taylor_block;      /* direct method: samples per Taylor block of the factored
+                                  kernel in the last map (64, or 256 when the Doppler spread
+                                  over the chosen tiles allows it)                        */
+    int32_t _pad3;
 } geoloc_plan_info;
 
 /* ABI version of the loaded library (GEOLOC_ABI_VERSION when it matches). */
@@ -198,6 +202,14 @@ int geoloc_set_points_from_tiles(geoloc_plan_t plan, const double* lat_dev, cons
  * need more than four Taylor terms go there too). Errors: EINVAL (bad shape, shear or grid
  * kind / method). */
 int geoloc_set_tiling(geoloc_plan_t plan, int32_t tile_w, int32_t tile_h, int32_t shear, int32_t transpose);
+
+/* Fix the length of the factored kernel's Taylor blocks (Sec. III, Eq. (11): the Doppler
+ * phase over a block is expanded in powers of the sample offset from the block centre) for
+ * the maps that follow: 64 samples, or 256 (four 64-sample blocks whose moments are moved to
+ * the long block's centre and summed, fewer per-point steps, more Taylor terms for the same
+ * Doppler spread); 0 returns to the per-map choice from the geometry. The map is the same
+ * function of the inputs to FP32 rounding. Errors: EINVAL (other lengths). */
+int geoloc_set_taylor_block(geoloc_plan_t plan, int32_t samples);
 
 /* Enable (nonzero) or disable per-kernel HIP-event timing of subsequent maps; either
  * way the accumulated times in geoloc_info are reset. Events are recorded on the map's

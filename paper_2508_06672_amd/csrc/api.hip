@@ -82,6 +82,8 @@ struct geoloc_plan_s {
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
     bool use_fact = false;           // factored direct kernel (method GEOLOC_DIRECT_FP32)
     bool fact_wide = false;          // its variant with up to 6 Taylor terms (wide Doppler spreads)
+    int32_t fact_sub = 1;            // 64-sample sub-blocks per Taylor block of the factored kernel (1 or 4)
+    int32_t taylor_fixed = 0;        // geoloc_set_taylor_block: that many sub-blocks (0: chosen per map)
     int32_t n_segs = 1, seg_len = 0; // factored kernel: coherent segments per step (few tiles, long steps)
     float2* d_cpart = nullptr;       // [n_segs][n_pairs * kc][P] complex partial sums
     // detection (allocated by the first geoloc_detect)
@@ -291,16 +293,24 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // VALU work per correlation summed over the pairs, counting the lanes its tiles leave
 // outside the grid. The lag moments cost about (8 + 4Q) instructions per lag pair and
 // sample, shared by the tile's cells (waves without a (block, lag pair) item skip them),
-// and the per-point combination about (4Q + 6) / 64 (LINEAR; fewer for ROUND, more for
-// SINC); a tile that the factored kernel would defer costs about 13. A tiling whose launch
-// has fewer than 768 workgroups (three per CU) is charged for the idle share of the chip,
-// and SINC keeps to 256-cell tiles at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
+// and the per-point combination about (4Q + 6) / B per Taylor block of B samples (LINEAR;
+// fewer for ROUND, more for SINC); a tile that the factored kernel would defer costs about
+// 13. Blocks of 256 samples (four 64-sample sub-blocks whose moments are moved to the long
+// block's centre and summed) cut the per-point share fourfold but need more Taylor terms
+// for the same Doppler spread; both block lengths are priced. A tiling whose launch has
+// fewer than 768 workgroups (three per CU) is charged for the idle share of the chip, and
+// SINC keeps to 256-cell tiles at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
-// are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
+// are counted 1.5 times, and the variant is launched when the chosen tiling needs them. A
+// fixed tiling (geoloc_set_tiling) keeps its shape and never takes the wide variant; only
+// its block length is chosen.
 void choose_tiling(geoloc_plan_t p, const double* states) {
-    p->tiling = p->base_tiling;
+    p->tiling = p->tiling_fixed ? p->fixed_tiling : p->base_tiling;
     p->fact_wide = false;
-    if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 || p->tile_shapes.empty()) return;
+    p->fact_sub = 1;
+    if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 ||
+        (p->tile_shapes.empty() && !p->tiling_fixed))
+        return;
     const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
     const bool has_r = p->rows >= 3, has_c = p->cols >= 3;
     // per pair, a quadratic model of the delay D (samples) and the Doppler th (radians per
@@ -360,7 +370,8 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
                                                   : (p->delay_mode == GEOLOC_DELAY_ROUND ? 2.0 : 4.0) * Q + 6.0;
     };
     const double taps = p->delay_mode == GEOLOC_DELAY_SINC ? 8.0 : 2.0;   // lags each cell reads
-    auto cost = [&](const PointTiling& t, int* q_need) {
+    const int q_allowed = p->tiling_fixed ? 4 : 6;
+    auto cost = [&](const PointTiling& t, int sub, int* q_need) {
         double total = 0.0;
         *q_need = 0;
         const double sh = (double)t.shear / kShearOne;
@@ -382,10 +393,10 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             const bool tr = t.transpose != 0;
             const double H = spread(tr ? g[1] : g[0], tr ? g[0] : g[1], tr ? g[5] : g[4], tr ? g[4] : g[5], g[6]) + taps + 1.0;
             const double xr = 0.5 * spread(tr ? g[3] : g[2], tr ? g[2] : g[3], tr ? g[8] : g[7], tr ? g[7] : g[8], g[9]) *
-                              (0.5 * 64.0);
+                              (0.5 * 64.0 * sub);
             int Q = 0;
             double term = 1.0;
-            for (int q = 1; q <= 6 && xr < 1.0; ++q) {
+            for (int q = 1; q <= q_allowed && xr < 1.0; ++q) {
                 term *= xr / q;
                 if (term <= 5.9604645e-8) {
                     Q = q;
@@ -395,9 +406,12 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             double c = 13.0;
             if (Q > 0 && H <= 128.0) {
                 const int Hg = (int)std::ceil(H / 2.0);
-                const int NB = std::min(32, 256 / Hg);
-                const double waves = std::ceil(NB * Hg / 64.0);   // waves busy with moments
-                c = ((8.0 + 4.0 * Q) * waves * 64.0 / (NB * lanes) + combine(Q) / 64.0) * (Q > 4 ? 1.5 : 1.0);
+                const int NB = std::min(32 / sub, 256 / (sub * Hg));     // Taylor blocks per round
+                const double waves = std::ceil(NB * sub * Hg / 64.0);   // waves busy with moments
+                // per lane and sub-block: the shift to the long block's centre and the quad sums
+                const double extra = sub > 1 ? 2.0 * Q * (Q - 1) + 8.0 * Q : 0.0;
+                c = ((8.0 + 4.0 * Q + extra / 64.0) * waves * 64.0 / (NB * sub * lanes) + combine(Q) / (64.0 * sub)) *
+                    (Q > 4 ? 1.5 : 1.0);
                 *q_need = std::max(*q_need, Q);
             }
             total += weight[gi] * c;
@@ -405,7 +419,20 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         return total * (double)(t.tiles_x * t.tiles_y * lanes) / (double)p->P * fill(t);
     };
     int q_best = 0, q = 0;
-    double best = cost(p->base_tiling, &q_best);
+    std::vector<int> subs = {1, 4};
+    if (p->taylor_fixed) subs = {p->taylor_fixed};
+    p->fact_sub = subs[0];
+    double best = cost(p->tiling, subs[0], &q_best);
+    for (size_t i = 1; i < subs.size(); ++i) {
+        const int sub = subs[i];
+        const double c = cost(p->tiling, sub, &q);
+        if (c < 0.97 * best) {
+            best = c;
+            q_best = q;
+            p->fact_sub = sub;
+        }
+    }
+    if (p->tiling_fixed) return;
     for (const auto& shape : p->tile_shapes) {
         // the SINC combination is bound by per-point work, registers and LDS reads: 256-cell
         // tiles at most 8 cells wide (on the 1e6-point map 16-wide tiles ran 1.4x slower,
@@ -426,11 +453,14 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             PointTiling t = shape;
             t.shear = std::max(-kMaxShear, std::min(kMaxShear, sh));
             tiling_counts(t);
-            const double c = cost(t, &q);
-            if (c < 0.97 * best) {
-                best = c;
-                q_best = q;
-                p->tiling = t;
+            for (const int sub : subs) {
+                const double c = cost(t, sub, &q);
+                if (c < 0.97 * best) {
+                    best = c;
+                    q_best = q;
+                    p->tiling = t;
+                    p->fact_sub = sub;
+                }
             }
         }
     }
@@ -999,6 +1029,14 @@ int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t s
     return GEOLOC_OK;
 }
 
+int geoloc_set_taylor_block(geoloc_plan_t p, int32_t samples) {
+    if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
+    if (samples != 0 && samples != 64 && samples != 256)
+        return fail(GEOLOC_EINVAL, "Taylor block must be 0 (per map), 64 or 256 samples (got %d)", samples);
+    p->taylor_fixed = samples / 64;
+    return GEOLOC_OK;
+}
+
 int geoloc_set_timing(geoloc_plan_t p, int enable) {
     if (!plan_ok(p)) return fail(GEOLOC_ESTATE, "invalid plan");
     int rc = drain_spans(p);
@@ -1017,12 +1055,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
     hipStream_t s = (hipStream_t)in->stream;
     int rc = upload_states(p, in->rx_state, s);
     if (rc) return rc;
-    if (p->tiling_fixed) {
-        p->tiling = p->fixed_tiling;
-        p->fact_wide = false;   // tile-steps that need more than four Taylor terms are deferred
-    } else {
-        choose_tiling(p, in->rx_state);
-    }
+    choose_tiling(p, in->rx_state);
     TimedSpan whole{};
     if ((rc = span_begin(p, s, &whole, 3))) return rc;
     if (p->method == GEOLOC_CAF_BF16 || p->method == GEOLOC_CAF_FP16) {
@@ -1063,7 +1096,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.cpart = p->d_cpart;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
         if (p->use_fact) {
-            HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, p->fact_wide, s));
+            HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, p->fact_wide, p->fact_sub, s));
             if (a.n_segs > 1) {
                 // the segment reduction writes J itself: later passes add to it in place
                 HIP_TRY(launch_direct_seg_reduce(a, s));
@@ -1236,6 +1269,7 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     r.tile_transpose = p->tiling.transpose;
     r.step_segments = p->n_segs > 1 ? p->n_segs : 1;
     r.segment_len = p->n_segs > 1 ? p->seg_len : (int32_t)p->L;
+    r.taylor_block = 64 * p->fact_sub;
     *out = r;
     return GEOLOC_OK;
 }

@@ -132,8 +132,9 @@ __device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
     for (int t = 0; t < kSincTaps; ++t) w[t] *= inv;
 }
 
+// sub_blocks: 64-sample sub-blocks per Taylor block, 1 or 4
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
-                              hipStream_t s);
+                              int32_t sub_blocks, hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
 // J[p] = (J[p] if loading) + sum over items of |sum over segments of cpart|^2 (or |.|)
 // CFAR detection (k_cfar.hip): summed-area table of J in sat [rows][cols], then masked[p] =

@@ -109,11 +109,40 @@ __device__ inline void block_moments2(const float2* __restrict__ v, const float2
     }
 }
 
+// Moments about a point o samples before the block centre (the centre of the long block
+// that holds this sub-block): sum_r (r + o)^q z_r = sum_{i<=q} C(q, i) o^(q-i) G_i, taken
+// from the highest order down so that every G_i read is still the sub-block's own.
+template <int Q>
+__device__ inline void shift_moments(float2 (&G)[Q], float o) {
+#pragma unroll
+    for (int q = Q - 1; q >= 1; --q) {
+        float gr = G[q].x, gi = G[q].y;
+        float op = 1.f, binom = 1.f;
+#pragma unroll
+        for (int i = q - 1; i >= 0; --i) {
+            op *= o;                                        // o^(q - i)
+            binom = binom * (float)(i + 1) / (float)(q - i);   // C(q, i), a compile-time constant
+            const float w = binom * op;
+            gr = fmaf(w, G[i].x, gr);
+            gi = fmaf(w, G[i].y, gi);
+        }
+        G[q] = make_float2(gr, gi);
+    }
+}
+
+// Sum over the four lanes of a quad (lanes 4i .. 4i + 3), the same value in all four:
+// (v0 + v1) + (v2 + v3) in every lane, by two DPP quad permutations.
+__device__ inline float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+    return v;
+}
+
 // Values of one (tile, step) that both phases use.
 struct FactStep {
     int64_t n_step;        // first sample of the step
-    int dlo, Hs, NB, TB;   // lowest lag read, lag stride of s_G (even), blocks per round / per LDS tile
-    int my_b, my_l;        // this thread's (block, lag pair) item
+    int dlo, Hs, NB, TB;   // lowest lag read, lag stride of s_G (even), long blocks per round / per LDS tile
+    int my_b, my_l, my_s;  // this thread's (long block, lag pair, sub-block) item
     int seg_lo, seg_hi;    // sample range of the step this workgroup sums (the whole step
                            // unless the step is split into segments)
 };
@@ -121,7 +150,7 @@ struct FactStep {
 // Per-point values of one (tile, step).
 struct FactPoint {
     double cyc;            // FDOA in cycles per sample
-    float2 ERB;            // exp(j 2 pi cyc 64): the block weight's step
+    float2 ERB;            // exp(j 2 pi cyc B): the block weight's step
     float alpha;           // fractional lag
     float w[kSincTaps];    // windowed-sinc weights (SINC only)
     float c[kFQWide];      // Taylor coefficients of the Doppler deviation: |(j delta)^q / q!|
@@ -140,10 +169,15 @@ struct FactPoint {
 // weight of the tile's last block goes into C. For LINEAR the interpolation weights are
 // folded into the Taylor coefficients once per step: a_q m_q = ((1 - a) a_q) G_q(d0) +
 // (a a_q) G_q(d0 + 1), four FMAs per Taylor term and block.
-template <int kMode, int Q, int kPPT>
+// s_G seen through the LDS address space: the phase-2 reads must be ds_read, which the
+// compiler does not always infer by itself for the per-point pointers into s_G.
+typedef __attribute__((address_space(3))) const float lds_cf;
+
+template <int kMode, int Q, int kPPT, int kSub>
 __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
                           const FactStep& st, const FactPoint (&pt)[kPPT], float2* s_y, float2* s_v, float2* s_G,
                           const float2* s_rot, float (&cr)[kPPT], float (&ci)[kPPT]) {
+    constexpr int kLB = kSub * kFB;
     const int tid = threadIdx.x;
     const double centre = 0.5 * (double)(a.L - 1);
     const int Hs = st.Hs;
@@ -161,13 +195,13 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                 cf[k][0][q] = pt[k].c[q];
             }
         }
-    for (int s0 = st.seg_lo; s0 < st.seg_hi; s0 += st.TB * kFB) {
-        const int tl = min(st.TB * kFB, st.seg_hi - s0);
-        const int nblk = (tl + kFB - 1) / kFB;
+    for (int s0 = st.seg_lo; s0 < st.seg_hi; s0 += st.TB * kLB) {
+        const int tl = min(st.TB * kLB, st.seg_hi - s0);
+        const int nblk = (tl + kLB - 1) / kLB;     // long blocks
         __syncthreads();
         {
             const int64_t m0 = st.n_step + s0 + st.dlo;
-            const int len = nblk * kFB + Hs;
+            const int len = nblk * kLB + Hs;
             if (m0 >= 0 && m0 + len <= a.N) {          // uniform: the usual case, no bounds checks
                 const float2* __restrict__ ys = yj + m0;
                 for (int t = tid; t < len; t += 256) s_y[t] = ys[t];
@@ -178,11 +212,11 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                 }
             }
             const float2* __restrict__ xs = yi + st.n_step + s0;
-            for (int t = tid; t < nblk * kFB; t += 256) {
+            for (int t = tid; t < nblk * kLB; t += 256) {
                 float2 v = make_float2(0.f, 0.f);
                 if (t < tl) {
                     const float2 x = xs[t];
-                    const float2 rt = s_rot[t & (kFB - 1)];
+                    const float2 rt = s_rot[t & (kLB - 1)];
                     v = make_float2(x.x * rt.x - x.y * rt.y, x.x * rt.y + x.y * rt.x);
                 }
                 s_v[(t >> 6) * kFVS + (t & (kFB - 1))] = v;
@@ -193,24 +227,37 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) accr[k] = acci[k] = 0.f;
         for (int bb = 0; bb < nblk; bb += st.NB) {
-            // phase 1: item (my_b, my_l) forms the moments of block bb + my_b at lags my_l, my_l + 1
+            // phase 1: item (my_b, my_l, my_s) forms the moments of sub-block my_s of long block
+            // bb + my_b at lags my_l, my_l + 1; the kSub lanes of a long block (a quad, when
+            // kSub is 4) move theirs to the long block's centre and sum them
             const int b = bb + st.my_b;
-            if (st.my_b < st.NB && b < nblk) {
+            if (st.my_b < st.NB && b < nblk) {      // uniform over the lanes of a long block
                 float2 G[2][Q];
-                block_moments2<Q>(s_v + b * kFVS, s_y + b * kFB + st.my_l, G[0], G[1]);
+                const int sb = b * kSub + st.my_s;
+                block_moments2<Q>(s_v + sb * kFVS, s_y + sb * kFB + st.my_l, G[0], G[1]);
+                if constexpr (kSub > 1) {
+                    static_assert(kSub == 4, "sub-block sums are taken over a quad");
+                    const float o = ((float)st.my_s - 0.5f * (float)(kSub - 1)) * (float)kFB;
+                    shift_moments<Q>(G[0], o);
+                    shift_moments<Q>(G[1], o);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) G[t][q] = make_float2(quad_sum(G[t][q].x), quad_sum(G[t][q].y));
+                }
                 float4* dst = reinterpret_cast<float4*>(s_G + (st.my_b * Hs + st.my_l) * Q);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     const float2 u = G[(2 * i) / Q][(2 * i) % Q], w = G[(2 * i + 1) / Q][(2 * i + 1) % Q];
-                    dst[i] = make_float4(u.x, u.y, w.x, w.y);
+                    if (kSub == 1 || i % kSub == st.my_s) dst[i] = make_float4(u.x, u.y, w.x, w.y);
                 }
             }
             __syncthreads();
             // phase 2: every point folds its blocks of this round into acc
             const int nb = __builtin_amdgcn_readfirstlane(min(st.NB, nblk - bb));
-            const float2* g[kPPT];
+            const lds_cf* g[kPPT];   // [2 (t Q + q)] real, [2 (t Q + q) + 1] imaginary part
 #pragma unroll
-            for (int k = 0; k < kPPT; ++k) g[k] = s_G + pt[k].off * Q;
+            for (int k = 0; k < kPPT; ++k) g[k] = (const lds_cf*)(s_G + pt[k].off * Q);
             for (int w = 0; w < nb; ++w) {
 #pragma unroll
                 for (int k = 0; k < kPPT; ++k) {
@@ -223,9 +270,9 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                         if constexpr (kMode == GEOLOC_DELAY_SINC) {
 #pragma unroll
                             for (int t = 0; t < kSincTaps; ++t) {
-                                const float2 gt = g[k][t * Q + q];
-                                mr = fmaf(pt[k].w[t], gt.x, mr);
-                                mi = fmaf(pt[k].w[t], gt.y, mi);
+                                const float gtr = g[k][2 * (t * Q + q)], gti = g[k][2 * (t * Q + q) + 1];
+                                mr = fmaf(pt[k].w[t], gtr, mr);
+                                mi = fmaf(pt[k].w[t], gti, mi);
                             }
                         }
                         // (j delta)^q / q! is real for even q, imaginary for odd q
@@ -233,9 +280,8 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                         for (int t = 0; t < kT; ++t) {
                             float gr = mr, gi = mi;
                             if constexpr (kMode != GEOLOC_DELAY_SINC) {
-                                const float2 gv = g[k][t * Q + q];
-                                gr = gv.x;
-                                gi = gv.y;
+                                gr = g[k][2 * (t * Q + q)];
+                                gi = g[k][2 * (t * Q + q) + 1];
                             }
                             const float c = cf[k][t][q];
                             if (q & 1) {
@@ -249,13 +295,13 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                     }
                     accr[k] = sr;
                     acci[k] = si;
-                    g[k] += Hs * Q;
+                    g[k] += 2 * Hs * Q;
                 }
             }
             __syncthreads();
         }
         // the exact weight of the tile's last block turns acc into this tile's share of C
-        const double t_last = (double)s0 + (double)(nblk - 1) * kFB + 0.5 * (double)(kFB - 1) - centre;
+        const double t_last = (double)s0 + (double)(nblk - 1) * kLB + 0.5 * (double)(kLB - 1) - centre;
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
             const float2 W = cis_cycles(pt[k].cyc * t_last);
@@ -266,13 +312,17 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
 }
 
 // kMode: GEOLOC_DELAY_LINEAR, _ROUND or _SINC; kQMax: most Taylor terms; kPPT: points per
-// thread (tiles of 256 kPPT cells).
-template <int kMode, int kQMax, int kPPT>
-__global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
+// thread (tiles of 256 kPPT cells); kSub: 64-sample sub-blocks per Taylor block (1 or 4).
+// Three workgroups per CU (two for the wide variant, whose LDS allows no more): the register
+// budget is set to match, which the compiler does not always choose by itself.
+template <int kMode, int kQMax, int kPPT, int kSub>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kQMax > 4 ? 2 : 3))) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
+    constexpr int kLB = kSub * kFB;                   // samples per Taylor block
     __shared__ float2 s_y[kFT + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
-    __shared__ __align__(16) float2 s_G[kQMax * 512];   // [round block][lag][q], <= 512 (block, lag) slots
-    __shared__ float2 s_rot[kFB];
+    // [round block][lag][q]: a round holds at most 512 / kSub (block, lag) slots
+    __shared__ __align__(16) float2 s_G[kQMax * 512 / kSub];
+    __shared__ float2 s_rot[kLB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
     constexpr int kLanes = 256 * kPPT;
@@ -364,8 +414,8 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         }
         const int64_t spread = (int64_t)dhi - (int64_t)dlo;
         const float tbar = 0.5f * (tlo + thi);
-        const float xr = 0.5f * (thi - tlo) * (0.5f * kFB);
-        // smallest Q with (delta_max * 32)^Q / Q! <= tol (uniform over the workgroup)
+        const float xr = 0.5f * (thi - tlo) * (0.5f * kLB);
+        // smallest Q with (delta_max B / 2)^Q / Q! <= tol (uniform over the workgroup)
         int Q = 0;
         if (xr == xr && xr < 1.f) {
             float term = 1.f;
@@ -393,7 +443,7 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         st.n_step = (int64_t)(a.k0 + kk) * a.L;
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
-            pt[k].ERB = cis_cycles(pt[k].cyc * (double)kFB);
+            pt[k].ERB = cis_cycles(pt[k].cyc * (double)kLB);
             if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(pt[k].alpha, pt[k].w);
             // (j dl)^q / q! = j^q dl^q / q!: j^q is 1, j, -1, -j in turn
             const float dl = (float)(two_pi * pt[k].cyc - (double)tbar);
@@ -407,27 +457,31 @@ __global__ __launch_bounds__(256) void k_direct_fact(DirectArgs a, uint8_t* __re
         }
         st.dlo = dlo - kTapLo;
         st.Hs = 2 * Hg;
-        st.NB = min(kFTB, 256 / Hg);
-        st.TB = st.NB * (kFTB / st.NB);
-        st.my_b = tid / Hg;
-        st.my_l = 2 * (tid - st.my_b * Hg);
+        st.NB = min(kFTB / kSub, 256 / (kSub * Hg));
+        st.TB = st.NB * ((kFTB / kSub) / st.NB);
+        {
+            const int item = tid / kSub;
+            st.my_s = tid - item * kSub;
+            st.my_b = item / Hg;
+            st.my_l = 2 * (item - st.my_b * Hg);
+        }
         st.seg_lo = segmented ? seg * a.seg_len : 0;
         st.seg_hi = segmented ? min(a.L, (seg + 1) * a.seg_len) : a.L;
-        if (tid < kFB) {
+        if (tid < kLB) {
             float sn, cs;
-            sincosf(tbar * ((float)tid - 0.5f * (float)(kFB - 1)), &sn, &cs);
+            sincosf(tbar * ((float)tid - 0.5f * (float)(kLB - 1)), &sn, &cs);
             s_rot[tid] = make_float2(cs, sn);
         }
         float cr[kPPT], ci[kPPT];
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) cr[k] = ci[k] = 0.f;
         switch (Q) {
-            case 1: fact_step<kMode, 1, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 2: fact_step<kMode, 2, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 3: fact_step<kMode, 3, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 4: fact_step<kMode, 4, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
-            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4), kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
-            default: fact_step<kMode, kQMax, kPPT>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 1: fact_step<kMode, 1, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 2: fact_step<kMode, 2, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 3: fact_step<kMode, 3, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 4: fact_step<kMode, 4, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4), kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
+            default: fact_step<kMode, kQMax, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci); break;
         }
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
@@ -478,31 +532,39 @@ hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int kQMax, int kPPT>
+template <int kQMax, int kPPT, int kSub>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
     if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
     else if (delay_mode == GEOLOC_DELAY_SINC)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
     else
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
+}
+
+template <int kQMax, int kPPT>
+static void launch_fact_sub(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, int32_t sub, hipStream_t s) {
+    if (sub == 4)
+        launch_fact_q<kQMax, kPPT, 4>(a, deferred, delay_mode, s);
+    else
+        launch_fact_q<kQMax, kPPT, 1>(a, deferred, delay_mode, s);
 }
 
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
-                              hipStream_t s) {
+                              int32_t sub_blocks, hipStream_t s) {
     const int lanes = tile_lanes(a.tiling);
-    if (lanes != 256 && lanes != 512) return hipErrorInvalidValue;
+    if ((lanes != 256 && lanes != 512) || (sub_blocks != 1 && sub_blocks != 4)) return hipErrorInvalidValue;
     if (lanes == 512) {
         if (wide_doppler)
-            launch_fact_q<kFQWide, 2>(a, deferred, delay_mode, s);
+            launch_fact_sub<kFQWide, 2>(a, deferred, delay_mode, sub_blocks, s);
         else
-            launch_fact_q<kFQ, 2>(a, deferred, delay_mode, s);
+            launch_fact_sub<kFQ, 2>(a, deferred, delay_mode, sub_blocks, s);
     } else {
         if (wide_doppler)
-            launch_fact_q<kFQWide, 1>(a, deferred, delay_mode, s);
+            launch_fact_sub<kFQWide, 1>(a, deferred, delay_mode, sub_blocks, s);
         else
-            launch_fact_q<kFQ, 1>(a, deferred, delay_mode, s);
+            launch_fact_sub<kFQ, 1>(a, deferred, delay_mode, sub_blocks, s);
     }
     return hipGetLastError();
 }

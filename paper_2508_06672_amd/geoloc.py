@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgeoloc.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENAN, EUNSUPPORTED, ELAUNCH = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECT_FP32, CAF_BF16, CAF_FP16, DIRECT_FP32_POINTWISE = 0, 1, 2, 3
@@ -71,6 +71,7 @@ class geoloc_plan_info(ctypes.Structure):
         ("map_ms", ctypes.c_double),
         ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32), ("tile_shear", ctypes.c_int32),
         ("tile_transpose", ctypes.c_int32), ("step_segments", ctypes.c_int32), ("segment_len", ctypes.c_int32),
+        ("taylor_block", ctypes.c_int32), ("_pad3", ctypes.c_int32),
     ]
 
 
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
                                   ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), P(ctypes.c_float),
                                   P(ctypes.c_int32), _vp]
     lib.geoloc_set_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.geoloc_set_taylor_block.argtypes = [_vp, ctypes.c_int32]
     lib.geoloc_set_points_from_tiles.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                                  P(ctypes.c_int32), ctypes.c_int32, _vp]
     lib.geoloc_info.argtypes = [_vp, P(geoloc_plan_info)]
@@ -112,7 +114,7 @@ def load() -> ctypes.CDLL:
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
-                 "geoloc_detect", "geoloc_set_tiling", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
+                 "geoloc_detect", "geoloc_set_tiling", "geoloc_set_taylor_block", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
                  "geoloc_subbands"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
@@ -374,6 +376,11 @@ class Plan:
         """Fix the factored kernel's tiling (shear in 1/256 column per row); tile_w = 0 returns
         to the per-map choice."""
         _check(load().geoloc_set_tiling(self.handle, tile_w, tile_h, shear, transpose), "geoloc_set_tiling")
+
+    def set_taylor_block(self, samples: int = 0) -> None:
+        """Fix the factored kernel's Taylor block length (64 or 256 samples); 0 returns to
+        the per-map choice."""
+        _check(load().geoloc_set_taylor_block(self.handle, samples), "geoloc_set_taylor_block")
 
     def detect(self, J, guard: int, train: int, scale: float, max_detections: int = 16, nms_radius: int = 0,
                stream=None):

@@ -324,6 +324,40 @@ def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
             assert ei.value.status == G.EINVAL, bad
 
 
+@pytest.mark.parametrize("block,delay,spacing,step", [(64, 0, 500.0, 10_000), (256, 0, 500.0, 10_000),
+                                                     (256, 1, 2000.0, 10_000), (256, 2, 500.0, 10_000),
+                                                     (256, 0, 8000.0, 7_000), (256, 0, 500.0, 41_000)])
+def test_taylor_blocks_match_oracle(torch, G, block, delay, spacing, step):
+    """The factored kernel with Taylor blocks of 64 samples and of 256 (four 64-sample blocks
+    moved to the long block's centre and summed across a lane quad), fixed through
+    geoloc_set_taylor_block: steps of 10,000 samples end in a partial long block, 8 km cells
+    need more Taylor terms (part of the tile-steps go to the per-point pass), 41,000-sample
+    steps are split into segments. All match the oracle; bad lengths are rejected."""
+    wl = configs.MAP_1E6.with_(n_rows=37, n_cols=58, spacing_m=spacing, n_samples=3 * step, step_len=step)
+    scn = sim.make_scenario(wl, 90 + delay + block)
+    log(f"taylor block {block} delay {delay} spacing {spacing} step {step}")
+    Jo = oracle.map_scenario(scn, delay_mode=delay)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn, delay_mode=delay) as plan:
+        plan.set_taylor_block(block)
+        plan.set_timing(True)
+        Jg = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        info = plan.info()
+        log(f"  tile {info['tile_cols']}x{info['tile_rows']} segments {info['step_segments']} "
+            f"err_J = {err_J(Jg, Jo):.3g}, per-point pass {info['interp_ms']:.3f} ms")
+        assert info["taylor_block"] == block
+        assert err_J(Jg, Jo) <= DIRECT_TOL
+        check_argmax(Jg, Jo, DIRECT_TOL)
+        for bad in (1, 128, 512, -64):
+            with pytest.raises(G.GeolocError) as ei:
+                plan.set_taylor_block(bad)
+            assert ei.value.status == G.EINVAL, bad
+        plan.set_taylor_block(0)
+        J2 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        assert plan.info()["taylor_block"] in (64, 256)
+        assert err_J(J2, Jo) <= DIRECT_TOL
+
+
 def test_random_tilings_on_ragged_grids(torch, G):
     """Twenty seeded random tilings (shape, shear in 1/256 column per row, orientation) on
     grids of odd sizes, some narrower than a tile: every cell is covered exactly once and
