@@ -467,10 +467,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kQMax > 4 ?
         }
         st.seg_lo = segmented ? seg * a.seg_len : 0;
         st.seg_hi = segmented ? min(a.L, (seg + 1) * a.seg_len) : a.L;
-        if (tid < kLB) {
+        for (int t = tid; t < kLB; t += 256) {
             float sn, cs;
-            sincosf(tbar * ((float)tid - 0.5f * (float)(kLB - 1)), &sn, &cs);
-            s_rot[tid] = make_float2(cs, sn);
+            sincosf(tbar * ((float)t - 0.5f * (float)(kLB - 1)), &sn, &cs);
+            s_rot[t] = make_float2(cs, sn);
         }
         float cr[kPPT], ci[kPPT];
 #pragma unroll
