@@ -294,7 +294,7 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // outside the grid. The lag moments cost about (8 + 4Q) instructions per lag pair and
 // sample, shared by the tile's cells (waves without a (block, lag pair) item skip them),
 // and the per-point combination about (4Q + 6) / B per Taylor block of B samples (LINEAR;
-// fewer for ROUND, more for SINC); a tile that the factored kernel would defer costs about
+// fewer for ROUND, more for SINC), or the time of its LDS reads where that is longer; a tile that the factored kernel would defer costs about
 // 13. Blocks of 256 samples (four 64-sample sub-blocks whose moments are moved to the long
 // block's centre and summed) cut the per-point share fourfold but need more Taylor terms
 // for the same Doppler spread; both block lengths are priced. A tiling whose launch has
@@ -364,10 +364,14 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     auto fill = [&](const PointTiling& t) {
         return std::max(1.0, 768.0 / ((double)(t.tiles_x * t.tiles_y) * groups));
     };
-    // per-point instructions per block: Taylor terms times lags read, plus one Horner step
+    // per-point instructions per block: Taylor terms times lags read, plus one Horner step;
+    // or the LDS reads of those moments when they take longer (8 bytes per moment at 128
+    // bytes per CU-cycle against one 64-lane instruction per CU-cycle: 4 instructions' worth)
     auto combine = [&](int Q) {
-        return p->delay_mode == GEOLOC_DELAY_SINC ? 18.0 * Q + 6.0
-                                                  : (p->delay_mode == GEOLOC_DELAY_ROUND ? 2.0 : 4.0) * Q + 6.0;
+        const double reads = p->delay_mode == GEOLOC_DELAY_SINC ? 8.0 : (p->delay_mode == GEOLOC_DELAY_ROUND ? 1.0 : 2.0);
+        const double valu = p->delay_mode == GEOLOC_DELAY_SINC ? 18.0 * Q + 6.0
+                                                                : (p->delay_mode == GEOLOC_DELAY_ROUND ? 2.0 : 4.0) * Q + 6.0;
+        return std::max(valu, 4.0 * reads * Q);
     };
     const double taps = p->delay_mode == GEOLOC_DELAY_SINC ? 8.0 : 2.0;   // lags each cell reads
     const int q_allowed = p->tiling_fixed ? 4 : 6;

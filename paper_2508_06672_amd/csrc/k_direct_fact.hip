@@ -169,9 +169,11 @@ struct FactPoint {
 // weight of the tile's last block goes into C. For LINEAR the interpolation weights are
 // folded into the Taylor coefficients once per step: a_q m_q = ((1 - a) a_q) G_q(d0) +
 // (a a_q) G_q(d0 + 1), four FMAs per Taylor term and block.
-// s_G seen through the LDS address space: the phase-2 reads must be ds_read, which the
-// compiler does not always infer by itself for the per-point pointers into s_G.
-typedef __attribute__((address_space(3))) const float lds_cf;
+// s_G seen through the LDS address space as 8-byte vectors: the phase-2 reads must be
+// 64-bit ds_read, which the compiler does not always infer by itself for the per-point
+// pointers into s_G (it emitted flat loads, or 32-bit reads with a float pointer).
+typedef float lds_vec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const lds_vec2 lds_cv2;
 
 template <int kMode, int Q, int kPPT, int kSub>
 __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
@@ -255,9 +257,9 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
             __syncthreads();
             // phase 2: every point folds its blocks of this round into acc
             const int nb = __builtin_amdgcn_readfirstlane(min(st.NB, nblk - bb));
-            const lds_cf* g[kPPT];   // [2 (t Q + q)] real, [2 (t Q + q) + 1] imaginary part
+            const lds_cv2* g[kPPT];
 #pragma unroll
-            for (int k = 0; k < kPPT; ++k) g[k] = (const lds_cf*)(s_G + pt[k].off * Q);
+            for (int k = 0; k < kPPT; ++k) g[k] = (const lds_cv2*)(s_G + pt[k].off * Q);
             for (int w = 0; w < nb; ++w) {
 #pragma unroll
                 for (int k = 0; k < kPPT; ++k) {
@@ -270,9 +272,9 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                         if constexpr (kMode == GEOLOC_DELAY_SINC) {
 #pragma unroll
                             for (int t = 0; t < kSincTaps; ++t) {
-                                const float gtr = g[k][2 * (t * Q + q)], gti = g[k][2 * (t * Q + q) + 1];
-                                mr = fmaf(pt[k].w[t], gtr, mr);
-                                mi = fmaf(pt[k].w[t], gti, mi);
+                                const lds_vec2 gt = g[k][t * Q + q];
+                                mr = fmaf(pt[k].w[t], gt.x, mr);
+                                mi = fmaf(pt[k].w[t], gt.y, mi);
                             }
                         }
                         // (j delta)^q / q! is real for even q, imaginary for odd q
@@ -280,8 +282,9 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                         for (int t = 0; t < kT; ++t) {
                             float gr = mr, gi = mi;
                             if constexpr (kMode != GEOLOC_DELAY_SINC) {
-                                gr = g[k][2 * (t * Q + q)];
-                                gi = g[k][2 * (t * Q + q) + 1];
+                                const lds_vec2 gv = g[k][t * Q + q];
+                                gr = gv.x;
+                                gi = gv.y;
                             }
                             const float c = cf[k][t][q];
                             if (q & 1) {
@@ -295,7 +298,7 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                     }
                     accr[k] = sr;
                     acci[k] = si;
-                    g[k] += 2 * Hs * Q;
+                    g[k] += Hs * Q;
                 }
             }
             __syncthreads();
