@@ -315,11 +315,13 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
 }
 
 // kMode: GEOLOC_DELAY_LINEAR, _ROUND or _SINC; kQMax: most Taylor terms; kPPT: points per
-// thread (tiles of 256 kPPT cells); kSub: 64-sample sub-blocks per Taylor block (1 or 4).
-// Three workgroups per CU (two for the wide variant, whose LDS allows no more): the register
-// budget is set to match, which the compiler does not always choose by itself.
-template <int kMode, int kQMax, int kPPT, int kSub>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kQMax > 4 ? 2 : 3))) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
+// thread (tiles of 256 kPPT cells); kSub: 64-sample sub-blocks per Taylor block (1 or 4);
+// kWaves: waves per SIMD the register budget is set for (which the compiler does not always
+// choose by itself). Three workgroups per CU, two for the wide variant (its LDS allows no
+// more); with 256-sample blocks the LDS allows four, at 128 VGPRs, whose spills fall in the
+// per-item set-up: the launcher takes that budget where items are long.
+template <int kMode, int kQMax, int kPPT, int kSub, int kWaves>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     constexpr int kLB = kSub * kFB;                   // samples per Taylor block
     __shared__ float2 s_y[kFT + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
@@ -535,15 +537,28 @@ hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Items of at least this many samples (a step, or a segment of one) take the four-wave
+// budget in LINEAR mode; shorter ones pay its spills too often (on the 1e6-point map, steps
+// of 10,000 samples, it ran 2 % slower, while 250,000-sample steps ran 23 % faster).
+constexpr int64_t kLongItem = 32768;
+
 template <int kQMax, int kPPT, int kSub>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
-    if (delay_mode == GEOLOC_DELAY_ROUND)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
-    else if (delay_mode == GEOLOC_DELAY_SINC)
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
-    else
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT, kSub>), grid, block, 0, s, a, deferred);
+    constexpr int kW = kQMax > 4 ? 2 : (kSub == 4 ? 4 : 3);
+    if (delay_mode == GEOLOC_DELAY_ROUND) {
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
+    } else if (delay_mode == GEOLOC_DELAY_SINC) {
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
+    } else if constexpr (kW == 4) {
+        const int64_t item = a.n_segs > 1 ? (int64_t)a.seg_len : (int64_t)a.L;
+        if (item < kLongItem)
+            hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT, kSub, 3>), grid, block, 0, s, a, deferred);
+        else
+            hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT, kSub, 4>), grid, block, 0, s, a, deferred);
+    } else {
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_LINEAR, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
+    }
 }
 
 template <int kQMax, int kPPT>
