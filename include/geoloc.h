@@ -207,8 +207,9 @@ int geoloc_set_tiling(geoloc_plan_t plan, int32_t tile_w, int32_t tile_h, int32_
  * phase over a block is expanded in powers of the sample offset from the block centre) for
  * the maps that follow: 64 samples, or 256 (four 64-sample blocks whose moments are moved to
  * the long block's centre and summed, fewer per-point steps, more Taylor terms for the same
- * Doppler spread); 0 returns to the per-map choice from the geometry. The map is the same
- * function of the inputs to FP32 rounding. Errors: EINVAL (other lengths). */
+ * Doppler spread); 0 returns to the per-map choice from the geometry (for POINTS grids, which
+ * have no per-map choice, 64). The map is the same function of the inputs to FP32 rounding.
+ * Errors: EINVAL (other lengths). */
 int geoloc_set_taylor_block(geoloc_plan_t plan, int32_t samples);
 
 /* Enable (nonzero) or disable per-kernel HIP-event timing of subsequent maps; either

@@ -309,8 +309,10 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     p->fact_wide = false;
     p->fact_sub = 1;
     if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32 ||
-        (p->tile_shapes.empty() && !p->tiling_fixed))
+        (p->tile_shapes.empty() && !p->tiling_fixed)) {
+        if (p->taylor_fixed) p->fact_sub = p->taylor_fixed;   // POINTS plans: the caller's block length
         return;
+    }
     const int64_t r0 = p->rows / 2, c0 = p->cols / 2, k = p->K / 2;
     const bool has_r = p->rows >= 3, has_c = p->cols >= 3;
     // per pair, a quadratic model of the delay D (samples) and the Doppler th (radians per

@@ -54,7 +54,8 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals the
     full-grid map at those cells to FP32 rounding (the full grid may use sheared tiles, so
     the sums group differently), as does the per-point kernel; the same points set on the
-    device from the tile list give the same map bit for bit, a tile index outside the grid
+    device from the tile list give the same map bit for bit (and within rounding with 256-sample
+    Taylor blocks), a tile index outside the grid
     gives NaN, and bad sizes are rejected. When the chosen tiles contain the full map's peak
     the refined peak is that peak."""
     from paper_2508_06672_amd import geoloc
@@ -83,6 +84,14 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
     prop.refine.set_points_from_tiles(lat_d, lon_d, P.TILE, tiles)
     Jd = prop.refine.map(caps, states).cpu().numpy()
     assert np.array_equal(Jd, Jr)
+    # a POINTS plan takes a fixed Taylor block length too
+    prop.refine.set_taylor_block(256)
+    J256 = prop.refine.map(caps, states).cpu().numpy().astype(np.float64)
+    assert prop.refine.info()["taylor_block"] == 256
+    assert float(np.max(np.abs(J256 - Jf[idx]))) <= 2e-5 * float(Jf.max())
+    prop.refine.set_taylor_block(0)
+    assert np.array_equal(prop.refine.map(caps, states).cpu().numpy(), Jr)
+    assert prop.refine.info()["taylor_block"] == 64
     bad = list(tiles)
     bad[3] = (wl.n_rows // P.TILE) * (wl.n_cols // P.TILE)      # one past the last tile
     prop.refine.set_points_from_tiles(lat_d, lon_d, P.TILE, bad)
