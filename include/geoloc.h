@@ -49,7 +49,7 @@ extern "C" {
 #define GEOLOC_EDEVICE      -3   /* no usable gfx950 device */
 #define GEOLOC_ESTATE       -4   /* call out of order (e.g. plan already destroyed) */
 #define GEOLOC_ENAN         -5   /* NaN found in a map by geoloc_argmax */
-#define GEOLOC_EUNSUPPORTED -6   /* valid request this build does not implement */
+#define GEOLOC_EUNSUPPORTED -6   /* valid request the library does not implement */
 #define GEOLOC_ELAUNCH      -7   /* a HIP runtime call or kernel launch failed */
 
 /* method */
