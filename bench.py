@@ -146,30 +146,49 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     return flops, units, deferred, total
 
 
-def cpu_baseline(scn, seconds: float = 15.0, max_points: int = 16384):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scn, seconds: float = 15.0, max_points: int = 16384, seconds_1t: float = 4.0):
+    """The FP64 oracle on the host cores (sampled points of the benchmark map, every sample),
+    with all the cores this process may use and with one thread."""
     import numpy as np
     import oracle
     wl = scn.workload
     cores = len(os.sched_getaffinity(0))
-    oracle.set_threads(cores)
     rng = np.random.Generator(np.random.PCG64(2024))
 
-    def run(n):
+    def run(n, threads):
+        oracle.set_threads(threads)
         idx = rng.choice(wl.n_points, n, replace=False)
         r, c = np.divmod(idx, wl.n_cols)
         t0 = time.perf_counter()
         oracle.map_points(scn.lat[r], scn.lon[c], scn.captures, scn.states, wl.step_len, wl.fs_hz, wl.fc_hz)
         return time.perf_counter() - t0
 
+    t1 = run(4, 1)
+    n1 = int(max(4, min(512, 4 * seconds_1t / max(t1, 1e-3))))
+    t1 = run(n1, 1)
+    rate_1t = n1 * wl.n_samples * len(wl.pairs) / t1
     n0 = max(cores, 32)
-    t0 = run(n0)
+    t0 = run(n0, cores)
     n = int(min(max_points, max(n0, n0 * seconds / max(t0, 1e-3))))
-    log(f"cpu baseline: calibration {n0} pts in {t0:.2f}s -> timing {n} pts")
-    t = run(n)
+    log(f"cpu baseline: 1 thread {n1} pts in {t1:.2f}s; calibration {n0} pts in {t0:.2f}s -> timing {n} pts")
+    t = run(n, cores)
     units = n * wl.n_samples * len(wl.pairs)
     return {"value": units / t, "unit": UNIT, "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "value_1_thread": rate_1t,
             "sample": f"{n} random points of the {wl.n_rows}x{wl.n_cols} grid x all {wl.n_samples} samples "
-                      f"({units:.3g} correlations in {t:.1f} s, FP64 C/OpenMP)"}
+                      f"({units:.3g} correlations in {t:.1f} s, FP64 C/OpenMP; 1 thread: {n1} points in "
+                      f"{t1:.1f} s)"}
 
 
 MFMA_PEAK_TFLOPS = 2500.0         # MI355X dense BF16 / FP16 MFMA
@@ -184,6 +203,7 @@ def cell_dist(a: int, b: int, n_cols: int) -> int:
 def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str, steps: int):
     """Time the CAF-table map on the same inputs and compare it with the direct map."""
     import numpy as np
+    from paper_2508_06672_amd import agreement as A
     wl = scn.workload
     m = geoloc.CAF_BF16 if method == "bf16" else geoloc.CAF_FP16
     plan = geoloc.Plan.for_scenario(scn, method=m)
@@ -211,6 +231,7 @@ def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str
            "err_vs_direct": float(np.max(np.abs(Jc - Jd)) / np.max(Jd)),
            "argmax_cell_dist": min(cell_dist(idx[0], a_direct, wl.n_cols),
                                    cell_dist(idx[0], mirror_cell(scn, a_direct), wl.n_cols)),
+           "rule": A.classify(Jd, wl.n_cols, int(idx[0]), a_direct, CAF_EPS, mirror_cell(scn, a_direct)),
            "window": {"lag_lo": info["caf_lag_lo"], "lags": info["caf_lags"], "bins": info["caf_bins"],
                       "nu_lo_hz": info["caf_nu_lo_hz"], "nu_hi_hz": info["caf_nu_hi_hz"]},
            "kernel_ms": {"setup": info["geometry_ms"] / max(1, info["timed_maps"]), "gemm": gemm_ms,
@@ -225,36 +246,73 @@ def caf_leg(geoloc, torch, scn, caps, J_direct, a_direct, ms_direct, method: str
 def mirror_cell(scn, a: int) -> int:
     """Grid cell of the reflection of cell a through the receivers' orbital plane: with
     every receiver in that plane and a non-rotating Earth, J(a) = J(mirror(a)) exactly."""
+    from paper_2508_06672_amd import agreement
+    return agreement.mirror_cell(scn.workload, scn.lat, scn.lon, a)
+
+
+CAF_EPS = 1e-2      # tolerance of the BF16 / FP16 CAF-table map
+
+
+def _simulate_job(args):
+    """One seeded scenario in a CPU worker (the pool is forked before the GPU is touched)."""
     from paper_2508_06672_amd import sim
-    r, c = divmod(int(a), scn.lon.size)
-    mr, mc = sim.nearest_cell(scn.lat, scn.lon, *sim.mirror_latlon(scn.workload, scn.lat[r], scn.lon[c]))
-    return mr * scn.lon.size + mc
+    wl, seed = args
+    scn = sim.make_scenario(wl, seed)
+    return seed, scn.lat, scn.lon, scn.states, scn.captures, scn.emitters[0].waveform
 
 
-def agreement(geoloc, torch, wl, seeds, tol: float = 1e-2):
-    """Fraction of seeded scenarios whose BF16 CAF peak is within one cell of the direct
-    FP32 peak or of its orbital-plane mirror (an exact tie of the map), and the fraction
-    where it is at least tol-optimal on the direct map."""
+def agreement(geoloc, torch, wl, seeds, pool, eps: float = CAF_EPS, out_path=None):
+    """The BF16 and FP16 CAF maps' peaks against the direct FP32 map's on seeded scenarios
+    of the benchmark workload: margin of the direct map (its peak against everything
+    outside the 3 x 3 cells around it and around its orbital-plane mirror), well-conditioned
+    when the margin exceeds 2 eps; within one cell of the direct peak or its mirror;
+    eps-optimal (J_direct at the CAF peak >= (1 - eps) J_direct max)."""
     import numpy as np
-    from paper_2508_06672_amd import sim
-    within = optimal = 0
-    for sd in seeds:
-        scn = sim.make_scenario(wl, sd)
-        caps = torch.from_numpy(scn.captures).cuda()
-        with geoloc.Plan.for_scenario(scn) as pd, geoloc.Plan.for_scenario(scn, method=geoloc.CAF_BF16) as pc:
-            Jd = pd.map(caps, scn.states)
-            ad = int(pd.argmax(Jd)[0][0])
-            Jc = pc.map(caps, scn.states)
-            ac = int(pc.argmax(Jc)[0][0])
-            Jd = Jd.cpu().numpy()
-        w = min(cell_dist(ac, ad, wl.n_cols), cell_dist(ac, mirror_cell(scn, ad), wl.n_cols)) <= 1
-        o = Jd[ac] >= (1 - 2 * tol) * Jd[ad]
-        within += w
-        optimal += (w or o)
-        log(f"  agreement seed {sd}: caf {ac} direct {ad} within1={w} tol-optimal={o}")
-    n = len(seeds)
-    return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "within_one_cell_or_mirror": within / n,
-            "within_one_cell_or_tol_optimal": optimal / n}
+    from paper_2508_06672_amd import agreement as A, sim
+    jobs = [(wl, s) for s in seeds]
+    it = pool.imap(_simulate_job, jobs, chunksize=2) if pool is not None else map(_simulate_job, jobs)
+    scn0 = sim.make_scenario(wl, seeds[0])
+    plans = {"direct": geoloc.Plan.for_scenario(scn0), "bf16": geoloc.Plan.for_scenario(scn0, method=geoloc.CAF_BF16),
+             "fp16": geoloc.Plan.for_scenario(scn0, method=geoloc.CAF_FP16)}
+    recs = []
+    t0 = time.time()
+    try:
+        for seed, lat, lon, states, capn, wf in it:
+            caps = torch.from_numpy(capn).cuda()
+            for p in plans.values():
+                p.set_grid(lat, lon)
+            Jd = plans["direct"].map(caps, states)
+            ad = int(plans["direct"].argmax(Jd)[0][0])
+            Jh = Jd.cpu().numpy().astype(np.float64)
+            mir = A.mirror_cell(wl, lat, lon, ad)
+            rec = {"seed": seed, "waveform": wf}
+            for m in ("bf16", "fp16"):
+                Jc = plans[m].map(caps, states)
+                ac = int(plans[m].argmax(Jc)[0][0])
+                c = A.classify(Jh, wl.n_cols, ac, ad, eps, mir)
+                c["err_vs_direct"] = float(np.max(np.abs(Jc.cpu().numpy() - Jh)) / np.max(Jh))
+                rec[m] = c
+            recs.append(rec)
+            b = rec["bf16"]
+            log(f"  agreement seed {seed} {wf:5s}: margin {b['margin']:.2e} bf16 {b['cell_dist']} cells "
+                f"(eps-opt {b['eps_optimal']}) fp16 {rec['fp16']['cell_dist']} cells")
+    finally:
+        for p in plans.values():
+            p.close()
+    out = {"workload": wl.name, "seeds": f"{seeds[0]}..{seeds[-1]}", "eps": eps, "sim_and_maps_s": time.time() - t0}
+    for m in ("bf16", "fp16"):
+        out[m] = A.summarise([r[m] for r in recs], eps)
+        out[m]["by_waveform"] = {wf: A.summarise([r[m] for r in recs if r["waveform"] == wf], eps)
+                                 for wf in sorted({r["waveform"] for r in recs})}
+        miss = [r for r in recs if r[m]["well_conditioned"] and not r[m]["within_one"]]
+        out[m]["misses_well_conditioned"] = [{"seed": r["seed"], "margin": r[m]["margin"],
+                                              "err_vs_direct": r[m]["err_vs_direct"],
+                                              "cell_dist": r[m]["cell_dist"]} for r in miss]
+        out[m]["max_err_vs_direct"] = max(r[m]["err_vs_direct"] for r in recs)
+    if out_path:
+        with open(out_path, "w") as fh:
+            json.dump({"summary": out, "records": recs}, fh)
+    return out
 
 
 def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
@@ -291,7 +349,7 @@ def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
     return {"batch": batch, "ms": ms, "samples_per_s": batch / (ms / 1e3), "params": int(theta.size)}
 
 
-def learned_leg(geoloc, seeds):
+def learned_leg(geoloc, seeds, pool=None, out_path=None):
     """The learned tile proposal with its stored weights and calibrated fallback on held-out
     proposal scenarios: median time against the full plain map of the same scenario, and
     how often its argmax agrees with the full map's (within one cell, on the orbital-plane
@@ -303,17 +361,22 @@ def learned_leg(geoloc, seeds):
     wl = P.TRAIN_WL
     prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"))
     try:
-        res = P.evaluate(prop, wl, seeds, None)
+        res = P.evaluate(prop, wl, seeds, pool)
     finally:
         prop.close()
         net.close()
+    if out_path:
+        with open(out_path, "w") as fh:
+            json.dump(res, fh)
     L, A = res["learned"], res["coarse_top16_ablation"]
     train = train_step_leg(geoloc, theta)
     return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"], "train_step": train,
-            "threshold": meta["threshold"], "full_map_median_ms": res["full_map_median_ms"],
+            "threshold": meta["threshold"], "n_train": meta.get("n_train"), "params": int(theta.size),
+            "full_map_median_ms": res["full_map_median_ms"],
             "median_ms": L["median_ms"], "speedup_vs_full_median": L["speedup_vs_full_median"],
-            "agree_rate": L["agree_rate"], "fallback_rate": L["fallback_rate"],
-            "ablation_agree_rate": A["agree_rate"], "ablation_speedup_vs_full_median": A["speedup_vs_full_median"]}
+            "agree_rate": L["agree_rate"], "fallback_rate": L["fallback_rate"], "rule": L["rule"],
+            "ablation_agree_rate": A["agree_rate"], "ablation_rule": A["rule"],
+            "ablation_speedup_vs_full_median": A["speedup_vs_full_median"]}
 
 
 def delay_modes_leg(geoloc, torch, scn, caps):
@@ -337,6 +400,101 @@ def delay_modes_leg(geoloc, torch, scn, caps):
                              f"{' transposed' if info['tile_transpose'] else ''}", "taylor_block": info["taylor_block"]}
     for name in ("linear", "round"):
         out[name]["peak_vs_sinc"] = out[name]["peak"] / out["sinc"]["peak"]
+    return out
+
+
+def _timed(torch, fn, reps: int):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def c3_leg(geoloc, torch, seeds=(0, 1, 2, 3), reps: int = 5):
+    """The CAF table on the small workload's inputs: 512 integer lags x 256 Doppler bins,
+    the literal +-40 kHz window and the window fitted to the footprint, BF16 and FP16, at the
+    stated 2 x 10,000-sample split and the native 5 x 4,000 split, against the plain FP32
+    map of the same split on the GPU (the FP64-oracle errors are logged by the GPU tests).
+    Reports the worst normalised |J error| over the seeds, the map times and the GEMM's
+    share of the MFMA peak."""
+    import numpy as np
+    from paper_2508_06672_amd import configs, sim
+    out = {}
+    for split, wl in (("2x10000", configs.CAF_SMALL), ("5x4000", configs.SMALL)):
+        for win in ("fitted", "literal_40kHz"):
+            for m in ("bf16", "fp16"):
+                kw = dict(method=geoloc.CAF_BF16 if m == "bf16" else geoloc.CAF_FP16, caf_lags=configs.CAF_LAGS,
+                          caf_bins=configs.CAF_BINS)
+                if win != "fitted":
+                    kw.update(caf_nu_lo_hz=configs.CAF_LITERAL_WINDOW_HZ[0], caf_nu_hi_hz=configs.CAF_LITERAL_WINDOW_HZ[1])
+                errs, ms_c, ms_d, gemm = [], [], [], []
+                for sd in seeds:
+                    scn = sim.make_scenario(wl, sd)
+                    caps = torch.from_numpy(scn.captures).cuda()
+                    with geoloc.Plan.for_scenario(scn) as pd, geoloc.Plan.for_scenario(scn, **kw) as pc:
+                        td, Jd = _timed(torch, lambda: pd.map(caps, scn.states), reps)
+                        pc.set_timing(True)
+                        tc, Jc = _timed(torch, lambda: pc.map(caps, scn.states), reps)
+                        info = pc.info()
+                    Jd = Jd.cpu().numpy().astype(np.float64)
+                    errs.append(float(np.max(np.abs(Jc.cpu().numpy() - Jd)) / np.max(Jd)))
+                    ms_c.append(tc)
+                    ms_d.append(td)
+                    gemm.append(info["correlate_ms"] / max(1, info["timed_maps"]))
+                flop = 8.0 * info["caf_lags"] * wl.n_samples * info["caf_bins"] * len(wl.pairs)
+                out[f"{split}/{win}/{m}"] = {
+                    "max_err_vs_plain_fp32": max(errs), "errs": errs, "caf_map_ms": float(np.median(ms_c)),
+                    "plain_map_ms": float(np.median(ms_d)), "lags": info["caf_lags"], "bins": info["caf_bins"],
+                    "nu_window_hz": [info["caf_nu_lo_hz"], info["caf_nu_hi_hz"]],
+                    "gemm_ms": float(np.median(gemm)), "gemm_flop": flop,
+                    "gemm_mfma_frac": flop / (float(np.median(gemm)) / 1e3) / (MFMA_PEAK_TFLOPS * 1e12)}
+                log(f"  C3 {split} {win} {m}: max err vs plain {max(errs):.3g}, map {np.median(ms_c):.3f} ms "
+                    f"(plain {np.median(ms_d):.3f} ms)")
+    return out
+
+
+def continental_leg(geoloc, torch, seed: int = 0):
+    """The continental workload (4000 x 4000 cells at 0.5 km, 3 receivers and 3 pairs, 4e6
+    samples at 20 MHz, two emitters at -20 dB): the plain FP32 map and the BF16 CAF map, each
+    with its top-2 peaks (exclusion radius 8 cells), and whether the CAF peaks fall within one
+    cell of a plain peak or its orbital-plane mirror."""
+    import numpy as np
+    from paper_2508_06672_amd import agreement as A, configs, sim
+    wl = configs.CONTINENTAL
+    t0 = time.time()
+    scn = sim.make_scenario(wl, seed)
+    log(f"  continental simulated in {time.time() - t0:.0f} s")
+    caps = torch.from_numpy(scn.captures).cuda()
+    out = {"workload": wl.name, "units": wl.units, "seed": seed}
+    peaks = {}
+    for name, kw in (("direct_fp32", {}), ("caf_bf16", {"method": geoloc.CAF_BF16})):
+        with geoloc.Plan.for_scenario(scn, **kw) as plan:
+            J = plan.map(caps, scn.states)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.map(caps, scn.states, J=J)
+            pk, pv = plan.argmax(J, top_k=2, nms_radius=8)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            peaks[name] = [int(p) for p in pk]
+            out[name] = {"map_ms": ms, "value": wl.units / (ms / 1e3), "top2": peaks[name],
+                         "top2_vals": [float(v) for v in pv]}
+            log(f"  continental {name}: {ms:.1f} ms, top-2 {peaks[name]}")
+    mirrors = [A.mirror_cell(wl, scn.lat, scn.lon, p) for p in peaks["direct_fp32"]]
+    refs = peaks["direct_fp32"] + mirrors
+    out["caf_bf16"]["top2_within_one_cell"] = [min(A.cell_dist(c, r, wl.n_cols) for r in refs) <= 1
+                                               for c in peaks["caf_bf16"]]
+    out["caf_bf16"]["speedup_vs_direct"] = out["direct_fp32"]["map_ms"] / out["caf_bf16"]["map_ms"]
+    true = [r * wl.n_cols + c for r, c in scn.true_cells]
+    out["direct_fp32"]["true_cells_within_one"] = [min(A.cell_dist(t, p, wl.n_cols) for p in
+                                                       peaks["direct_fp32"] + mirrors) <= 1 for t in true]
     return out
 
 
@@ -391,10 +549,18 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-caf", action="store_true", help="skip the CAF-table legs")
-    ap.add_argument("--agreement-seeds", type=int, default=8,
-                    help="scenarios (seeds 10000..) for the CAF-vs-direct argmax agreement")
-    ap.add_argument("--proposal-seeds", type=int, default=8,
-                    help="held-out scenarios for the learned-proposal leg (0 skips it)")
+    ap.add_argument("--agreement-seeds", type=int, default=200,
+                    help="scenarios (seeds 10000..) for the CAF-vs-direct argmax agreement (0 skips it)")
+    ap.add_argument("--proposal-seeds", type=int, default=100,
+                    help="held-out scenarios (seeds 1030000..) for the learned-proposal leg (0 skips it)")
+    ap.add_argument("--study", action="store_true",
+                    help="the full agreement study: 1000 CAF seeds and 300 learned-proposal seeds, with "
+                         "per-scenario records written under --study-out")
+    ap.add_argument("--study-out", default="gpurun_out", help="directory of the per-scenario study records")
+    ap.add_argument("--workers", type=int, default=16, help="CPU processes that simulate scenarios")
+    ap.add_argument("--no-c3", action="store_true", help="skip the CAF-table error leg on the small inputs")
+    ap.add_argument("--continental", action="store_true",
+                    help="also time the 4000 x 4000, 3-pair, 4e6-sample workload (direct and BF16 CAF, top-2)")
     ap.add_argument("--no-paper-scenario", action="store_true", help="skip the 58-capture scenario leg")
     ap.add_argument("--no-delay-modes", action="store_true", help="skip the ROUND / SINC delay-mode leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -404,6 +570,18 @@ def main() -> int:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this library has no multi-GPU path",
               file=sys.stderr)
         return 2
+
+    if args.study:
+        args.agreement_seeds, args.proposal_seeds = max(args.agreement_seeds, 1000), max(args.proposal_seeds, 300)
+    pool = None
+    if args.agreement_seeds > 0 or args.proposal_seeds > 0:
+        # simulator workers are forked before anything touches the GPU
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(max(1, min(args.workers, len(os.sched_getaffinity(0)))))
+    rec_dir = None
+    if args.study:
+        rec_dir = args.study_out
+        os.makedirs(rec_dir, exist_ok=True)
 
     import numpy as np
     import torch
@@ -486,7 +664,11 @@ def main() -> int:
             caf[m] = caf_leg(geoloc, torch, scn, caps, Jd, ad, ms, m, args.steps)
         if args.agreement_seeds > 0:
             log(f"caf agreement over {args.agreement_seeds} seeds")
-            caf["agreement_bf16"] = agreement(geoloc, torch, wl, list(range(10000, 10000 + args.agreement_seeds)))
+            caf["agreement"] = agreement(geoloc, torch, wl, list(range(10000, 10000 + args.agreement_seeds)), pool,
+                                         out_path=os.path.join(rec_dir, "agreement_caf.json") if rec_dir else None)
+        if not args.no_c3:
+            log("C3: CAF table on the small inputs")
+            caf["c3"] = c3_leg(geoloc, torch)
 
     modes = None
     if not args.no_delay_modes:
@@ -497,13 +679,21 @@ def main() -> int:
     if args.proposal_seeds > 0:
         from paper_2508_06672_amd import proposal as P
         log(f"learned proposal over {args.proposal_seeds} held-out scenarios")
-        learned = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.proposal_seeds)))
+        learned = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.proposal_seeds)), pool,
+                              out_path=os.path.join(rec_dir, "agreement_learned.json") if rec_dir else None)
 
     paper = None
     if not args.no_paper_scenario:
         log("58-capture scenario")
         paper = paper_leg(geoloc, torch)
 
+    continental = None
+    if args.continental:
+        log("continental workload")
+        continental = continental_leg(geoloc, torch)
+
+    if pool is not None:
+        pool.terminate()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scn, args.cpu_seconds)
@@ -527,6 +717,7 @@ def main() -> int:
         "delay_modes": modes,
         "learned": learned,
         "paper_scenario": paper,
+        "continental": continental,
     }
     print(json.dumps(out), flush=True)
     plan.close()

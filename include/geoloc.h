@@ -15,6 +15,7 @@
  *   D_k(p) = (tau_j - tau_i) f_s, nu_k(p) = f_j - f_i    (Eq. (7)-(9), delay in samples)
  *   LINEAR: yt_j[n] = (1-a) y_j[n+d0] + a y_j[n+d0+1], d0 = floor(D), a = D - d0
  *   ROUND : yt_j[n] = y_j[n + round(D)]  (Eq. (9); halves round away from zero)
+ *   SINC  : yt_j[n] = sum_{t=-3}^{4} w_t(a) y_j[n + d0 + t]  (eight-tap windowed sinc)
  *   y_j[m] = 0 for m outside [0, N).
  *
  * Conventions
@@ -28,7 +29,10 @@
  *     independent.
  *   - Flat point index = row * n_cols + col, rows = latitude (RECT grids); the
  *     position in the lat/lon arrays for POINTS grids.
- *   - Units: SI; angles are geocentric latitude / longitude in radians on a sphere.
+ *   - Units: SI; angles in radians: geocentric latitude / longitude on a sphere
+ *     (GEOLOC_EARTH_SPHERE), or geodetic latitude / longitude on the WGS-84 ellipsoid
+ *     (GEOLOC_EARTH_WGS84), heights along the ellipsoid normal. Receiver states are ECEF
+ *     in both cases.
  *   - Requires a gfx950 device; anything else returns GEOLOC_EDEVICE.
  */
 #ifndef GEOLOC_H
@@ -58,7 +62,10 @@ extern "C" {
                                     points (256 or 512 cells of a RECT grid in a slanted tile
                                     chosen per map, 256 consecutive points of a POINTS
                                     list), with a Taylor remainder of at
-                                    most 2^-24 of each 64-sample block's magnitude sum;
+                                    most 2^-24 of each Taylor block's magnitude sum (blocks
+                                    of 64 or 256 samples, chosen per map from the Doppler
+                                    spread over the tiles, or fixed by
+                                    geoloc_set_taylor_block);
                                     tiles whose lags or Doppler shifts spread too widely are
                                     summed point by point */
 #define GEOLOC_DIRECT_FP32_POINTWISE 3  /* the same map, every point summed on its own      */
@@ -110,7 +117,7 @@ typedef struct geoloc_desc {
     double earth_radius_m;     /* sphere radius (e.g. 6371000); unused for WGS-84         */
     double alt_m;              /* height of every candidate point above the surface       */
     int32_t method;            /* GEOLOC_DIRECT_FP32 / GEOLOC_CAF_BF16 / GEOLOC_CAF_FP16  */
-    int32_t delay_mode;        /* GEOLOC_DELAY_LINEAR / GEOLOC_DELAY_ROUND                */
+    int32_t delay_mode;        /* GEOLOC_DELAY_LINEAR / GEOLOC_DELAY_ROUND / GEOLOC_DELAY_SINC */
     int32_t accum_mode;        /* GEOLOC_ACC_POWER / GEOLOC_ACC_MAG                       */
     int32_t caf_lags;          /* CAF: integer lags per table; 0 -> fit to the footprint  */
     int32_t caf_bins;          /* CAF: Doppler bins per table; 0 -> 256                   */
@@ -276,6 +283,17 @@ int geoloc_argmax(geoloc_plan_t plan, const float* J_dev, int32_t top_k, int32_t
 int geoloc_detect(geoloc_plan_t plan, const float* J_dev, int32_t guard_cells, int32_t train_cells, double scale,
                   int32_t max_detections, int32_t nms_radius_cells, int64_t* idx_host, float* val_host,
                   float* noise_host, int32_t* n_found, void* stream);
+
+/* Threshold scale of geoloc_detect for a false-alarm probability (the threshold step of
+ * Algorithm 1, read as cell-averaging CFAR). For independent Gamma(L) noise cells, a cell x
+ * and the sum z of N training cells give x / (x + z) ~ Beta(L, N L), so the scale a with
+ * P(x > a z / N) = pfa is a = N b / (1 - b), b the (1 - pfa) quantile of Beta(L, N L).
+ * The quantile is found by bisection on the upper tail 1 - I_b(L, N L), the regularised
+ * incomplete beta function evaluated by its continued fraction (modified Lentz algorithm);
+ * for L = 1 it equals the closed form N (pfa^(-1/N) - 1). Host computation only: needs no
+ * device and no plan. *out (HOST) receives the scale. Errors: EINVAL (pfa outside (0, 1),
+ * n_train < 1, looks < 1, NULL out). */
+int geoloc_cfar_scale(double pfa, int32_t n_train, int32_t looks, double* out);
 
 int geoloc_info(geoloc_plan_t plan, geoloc_plan_info* out);
 

@@ -58,7 +58,9 @@ def detect(J: np.ndarray, guard: int, train: int, scale: float, k: int,
 
 
 def scale_for_pfa(pfa: float, n_train: int, looks: int = 1) -> float:
-    """Scale a with P(x > a mean(training)) = pfa for independent Gamma(looks) noise."""
-    from scipy.special import betaincinv
-    b = float(betaincinv(looks, n_train * looks, 1.0 - pfa))
+    """Scale a with P(x > a mean(training)) = pfa for independent Gamma(looks) noise. The
+    Beta quantile is taken from the upper tail itself (inverse of 1 - I_b), not as the
+    (1 - pfa) quantile, so that 1 - pfa does not round away the digits of a small pfa."""
+    from scipy.special import betainccinv
+    b = float(betainccinv(looks, n_train * looks, pfa))
     return n_train * b / (1.0 - b)

@@ -30,6 +30,15 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+int geoloc::set_last_error(int code, const char* msg) {
+    g_last_error = msg;
+    return code;
+}
+
+namespace {
+
 #define HIP_TRY(call)                                                                               \
     do {                                                                                            \
         hipError_t e_ = (call);                                                                     \
@@ -1241,6 +1250,76 @@ int geoloc_detect(geoloc_plan_t p, const float* J, int32_t guard, int32_t train,
         if (ok) ++n;
     }
     *n_found = n;
+    return GEOLOC_OK;
+}
+
+// Regularised incomplete beta function I_x(a, b) from its continued fraction
+//   I_x(a, b) = x^a (1 - x)^b / (a B(a, b)) * 1 / (1 + e_1 / (1 + e_2 / (1 + ...))),
+//   e_{2m+1} = -(a + m)(a + b + m) x / ((a + 2m)(a + 2m + 1)),
+//   e_{2m}   = m (b - m) x / ((a + 2m - 1)(a + 2m)),
+// (Abramowitz & Stegun 26.5.8), evaluated by the modified Lentz algorithm (Lentz 1976;
+// Thompson & Barnett 1986). The fraction converges fast for x < (a + 1) / (a + b + 2); above
+// that I_x(a, b) = 1 - I_{1-x}(b, a) is used, and `upper` asks for 1 - I_x(a, b) directly so
+// that small tail probabilities keep their relative precision.
+static double beta_cf(double a, double b, double x) {
+    constexpr double kTiny = 1e-300;
+    double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
+    if (std::fabs(d) < kTiny) d = kTiny;
+    d = 1.0 / d;
+    double f = d;
+    for (int m = 1; m <= 100000; ++m) {
+        const double e_even = m * (b - m) * x / ((a + 2.0 * m - 1.0) * (a + 2.0 * m));
+        d = 1.0 + e_even * d;
+        c = 1.0 + e_even / c;
+        if (std::fabs(d) < kTiny) d = kTiny;
+        if (std::fabs(c) < kTiny) c = kTiny;
+        d = 1.0 / d;
+        f *= c * d;
+        const double e_odd = -(a + m) * (a + b + m) * x / ((a + 2.0 * m) * (a + 2.0 * m + 1.0));
+        d = 1.0 + e_odd * d;
+        c = 1.0 + e_odd / c;
+        if (std::fabs(d) < kTiny) d = kTiny;
+        if (std::fabs(c) < kTiny) c = kTiny;
+        d = 1.0 / d;
+        const double delta = c * d;
+        f *= delta;
+        if (std::fabs(delta - 1.0) < 1e-16) break;
+    }
+    return f;
+}
+
+static double beta_inc(double a, double b, double x, bool upper) {
+    if (x <= 0.0) return upper ? 1.0 : 0.0;
+    if (x >= 1.0) return upper ? 0.0 : 1.0;
+    const double lfront = std::lgamma(a + b) - std::lgamma(a) - std::lgamma(b) + a * std::log(x) + b * std::log1p(-x);
+    if (x < (a + 1.0) / (a + b + 2.0)) {
+        const double v = std::exp(lfront) * beta_cf(a, b, x) / a;
+        return upper ? 1.0 - v : v;
+    }
+    const double v = std::exp(lfront) * beta_cf(b, a, 1.0 - x) / b;   // 1 - I_x(a, b)
+    return upper ? v : 1.0 - v;
+}
+
+int geoloc_cfar_scale(double pfa, int32_t n_train, int32_t looks, double* out) {
+    if (!out) return fail(GEOLOC_EINVAL, "NULL output");
+    if (!(pfa > 0.0 && pfa < 1.0)) return fail(GEOLOC_EINVAL, "false-alarm probability must be in (0, 1)");
+    if (n_train < 1 || looks < 1) return fail(GEOLOC_EINVAL, "need n_train >= 1 and looks >= 1");
+    // x / (x + z) ~ Beta(L, N L): find the b with P(Beta > b) = pfa by bisection on [0, 1]
+    // (the tail falls monotonically in b), then scale = N b / (1 - b).
+    const double a = (double)looks, bb = (double)n_train * (double)looks;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (beta_inc(a, bb, mid, true) > pfa)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const double b = 0.5 * (lo + hi);
+    const double scale = (double)n_train * b / (1.0 - b);
+    if (!std::isfinite(scale) || !(scale > 0.0)) return fail(GEOLOC_EINVAL, "no finite scale for this request");
+    *out = scale;
     return GEOLOC_OK;
 }
 

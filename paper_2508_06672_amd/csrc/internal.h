@@ -246,6 +246,8 @@ struct ArgmaxScratch {
 constexpr int kMaxTopK = 64;
 hipError_t launch_argmax(const float* J, int64_t P, int64_t cols, int32_t rect, int32_t radius, int32_t top_k,
                          ArgmaxScratch& s, hipStream_t st);
+// Record a detail string for geoloc_last_error() and return code.
+int set_last_error(int code, const char* msg);
 int32_t argmax_blocks(int64_t P);
 
 int32_t caf_extent_blocks(int64_t total);

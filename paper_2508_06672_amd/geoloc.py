@@ -113,9 +113,10 @@ def load() -> ctypes.CDLL:
     lib.geoloc_strerror.restype = ctypes.c_char_p
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+    lib.geoloc_cfar_scale.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
                  "geoloc_detect", "geoloc_set_tiling", "geoloc_set_taylor_block", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
-                 "geoloc_subbands"):
+                 "geoloc_subbands", "geoloc_cfar_scale"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -214,13 +215,16 @@ def geoloc_detect(plan: int, J_dev: int, guard: int, train: int, scale: float, m
     return idx[:n.value], val[:n.value], noise[:n.value]
 
 
+def geoloc_cfar_scale(pfa: float, n_train: int, looks: int = 1) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load().geoloc_cfar_scale(float(pfa), int(n_train), int(looks), ctypes.byref(out)), "geoloc_cfar_scale")
+    return out.value
+
+
 def cfar_scale(pfa: float, n_train: int, looks: int = 1) -> float:
-    """CFAR scale for false-alarm probability pfa with n_train training cells of independent
-    Gamma(looks) noise: the cell x and the training sum z give x / (x + z) ~ Beta(looks,
-    n_train looks), so scale = n_train b / (1 - b) with b its (1 - pfa) quantile."""
-    from scipy.special import betaincinv
-    b = float(betaincinv(looks, n_train * looks, 1.0 - pfa))
-    return n_train * b / (1.0 - b)
+    """CFAR threshold scale for false-alarm probability pfa with n_train training cells of
+    independent Gamma(looks) noise (computed by the library, geoloc_cfar_scale)."""
+    return geoloc_cfar_scale(pfa, n_train, looks)
 
 
 def cfar_training_cells(guard: int, train: int) -> int:

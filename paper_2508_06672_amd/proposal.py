@@ -35,7 +35,7 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from . import configs, sim
+from . import agreement, configs, sim
 
 COARSE = configs.PROPOSAL_COARSE
 TILE = configs.PROPOSAL_TILE
@@ -324,21 +324,16 @@ def calibrate(rec, target: float = 0.99, rule: str = "mass") -> dict:
 
 # --------------------------------------------------------------------------- evaluation
 
-def _cell_dist(a: int, b: int, n_cols: int) -> int:
-    ra, ca = divmod(int(a), n_cols)
-    rb, cb = divmod(int(b), n_cols)
-    return max(abs(ra - rb), abs(ca - cb))
+AGREE_EPS = 1e-4      # the refine map is the full map's own FP32 values at the chosen cells
 
 
-def _agrees(wl, lat, lon, a: int, a_full: int, J_full: np.ndarray, tol: float = 1e-4) -> bool:
-    """Within one cell of the full map's peak or of its orbital-plane mirror (an exact tie),
-    or tol-optimal on the full map."""
-    r, c = divmod(a_full, wl.n_cols)
-    mr, mc = sim.nearest_cell(lat, lon, *sim.mirror_latlon(wl, lat[r], lon[c]))
-    m = mr * wl.n_cols + mc
-    if min(_cell_dist(a, a_full, wl.n_cols), _cell_dist(a, m, wl.n_cols)) <= 1:
-        return True
-    return bool(J_full[a] >= (1 - 2 * tol) * J_full[a_full])
+def _agrees(wl, lat, lon, a: int, a_full: int, J_full: np.ndarray, eps: float = AGREE_EPS) -> dict:
+    """The peak a against the full plain map's peak (agreement.classify): margin of the full
+    map, within one cell of its peak or of that peak's orbital-plane mirror, eps-optimal;
+    'ok' is within one cell on a well-conditioned map and eps-optimal on any other."""
+    c = agreement.classify(J_full, wl.n_cols, a, a_full, eps, agreement.mirror_cell(wl, lat, lon, a_full))
+    c["ok"] = c["within_one"] if c["well_conditioned"] else (c["within_one"] or c["eps_optimal"])
+    return c
 
 
 def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
@@ -359,8 +354,9 @@ def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
             t0 = time.perf_counter()
             r = prop.run(caps, states, selector=sel)
             torch.cuda.synchronize()
-            out[sel] = {"ok": _agrees(wl, lat, lon, r["idx"], a_full, Jh), "fallback": r["fallback"],
-                        "score": r["score"], "t_ms": (time.perf_counter() - t0) * 1e3}
+            t_ms = (time.perf_counter() - t0) * 1e3
+            c = _agrees(wl, lat, lon, r["idx"], a_full, Jh)
+            out[sel] = {"ok": c["ok"], "rule": c, "fallback": r["fallback"], "score": r["score"], "t_ms": t_ms}
         recs.append(out)
         log(f"  seed {seed} {wf:5s} {snr:6.1f} dB: cnn ok={out['cnn']['ok']} fb={out['cnn']['fallback']} "
             f"score={out['cnn']['score']:.2f} | coarse ok={out['coarse']['ok']}")
@@ -376,6 +372,7 @@ def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
             by_wf[wf] = {"n": len(sub), "agree_rate": float(np.mean([r[sel]["ok"] for r in sub])),
                          "fallback_rate": float(np.mean([r[sel]["fallback"] for r in sub]))}
         return {"agree_rate": float(np.mean(ok)), "fallback_rate": float(np.mean(fb)),
+                "rule": agreement.summarise([r[sel]["rule"] for r in recs], AGREE_EPS),
                 "median_ms": float(np.median(t)), "speedup_vs_full_median": float(np.median(
                     [r["t_full_ms"] / r[sel]["t_ms"] for r in recs])), "by_waveform": by_wf}
     return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "workload": wl.name,

@@ -148,3 +148,27 @@ def test_subbands_validation_returns_einval():
     for c in cases:
         rc = lib.geoloc_subbands(c[0], c[1], c[2], c[3], c[4], c[5], None)
         assert rc == geoloc.EINVAL, (c, rc, geoloc.geoloc_last_error())
+
+
+def test_cfar_scale_matches_the_oracle():
+    """geoloc_cfar_scale (continued fraction of the incomplete beta, bisection) against the
+    oracle's Beta quantile (scipy) to 1e-9, over the window sizes and look counts the
+    detection uses; L = 1 also against the exponential closed form N (pfa^(-1/N) - 1)."""
+    from oracle import cfar
+    for pfa in (1e-2, 1e-3, 2e-3, 1e-6, 1e-9):
+        for n_train in (8, 48, 240, 920):
+            for looks in (1, 2, 8, 58):
+                got = geoloc.geoloc_cfar_scale(pfa, n_train, looks)
+                ref = cfar.scale_for_pfa(pfa, n_train, looks)
+                assert abs(got - ref) <= 1e-9 * ref, (pfa, n_train, looks, got, ref)
+            closed = n_train * (pfa ** (-1.0 / n_train) - 1.0)
+            assert abs(geoloc.geoloc_cfar_scale(pfa, n_train, 1) - closed) <= 1e-9 * closed
+
+
+@pytest.mark.parametrize("args", [(0.0, 10, 1), (1.0, 10, 1), (float("nan"), 10, 1), (1e-3, 0, 1), (1e-3, 10, 0)])
+def test_cfar_scale_rejects_bad_arguments(args):
+    lib = geoloc.load()
+    out = ctypes.c_double(-7.0)
+    assert lib.geoloc_cfar_scale(*args, ctypes.byref(out)) == geoloc.EINVAL
+    assert out.value == -7.0
+    assert lib.geoloc_cfar_scale(1e-3, 10, 1, None) == geoloc.EINVAL

@@ -48,7 +48,7 @@ def test_window_counts_at_edges_and_corners():
 
 def test_exponential_closed_form_of_the_scale():
     for N in (8, 24, 48, 120):
-        for pfa in (1e-2, 1e-4, 1e-6):
+        for pfa in (1e-2, 1e-4, 1e-6, 1e-9):
             a = cfar.scale_for_pfa(pfa, N, 1)
             assert a == pytest.approx(N * (pfa ** (-1.0 / N) - 1.0), rel=1e-9)
             assert (1.0 + a / N) ** (-N) == pytest.approx(pfa, rel=1e-9)
@@ -106,8 +106,10 @@ CFAR_MUTANTS = {
     "count_ignores_clipping": ("n = (r1 - r0 + 1) * (c1 - c0 + 1) - (g1 - g0 + 1) * (h1 - h0 + 1)",
                                "n = (2 * train + 1) ** 2 - (g1 - g0 + 1) * (h1 - h0 + 1)"),
     "threshold_on_sum": ("hit = (count > 0) & (J > scale * noise)", "hit = (count > 0) & (J > scale * noise * count)"),
-    "scale_looks_ignored": ("b = float(betaincinv(looks, n_train * looks, 1.0 - pfa))",
-                            "b = float(betaincinv(1, n_train, 1.0 - pfa))"),
+    "scale_looks_ignored": ("b = float(betainccinv(looks, n_train * looks, pfa))",
+                            "b = float(betainccinv(1, n_train, pfa))"),
+    "scale_lower_tail": ("b = float(betainccinv(looks, n_train * looks, pfa))",
+                         "b = float(betainccinv(looks, n_train * looks, 1.0 - pfa))"),
 }
 
 

@@ -1,5 +1,6 @@
 """Pins of the FP64 CNN oracle: a library convolution, central finite differences of
 the loss, the zero-weight special case, softmax-CE closed forms and Adam's first step."""
+import pytest
 import numpy as np
 import scipy.signal
 
@@ -81,3 +82,63 @@ def test_adam_first_step_is_sign_step():
     th, m, v = cnn.adam(np.zeros(3), np.zeros(3), np.zeros(3), g, 1, lr=0.01)
     # after one step m_hat = g and v_hat = g^2, so the update is -lr * g / (|g| + eps)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8))
+
+
+def test_adam_constant_gradient_takes_equal_steps():
+    """With a constant gradient the moments are m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2,
+    so the bias-corrected update is -lr g / (|g| + eps) at every step, not only the first:
+    this fixes both bias corrections at t = 2 and 3, where b^t differs from b."""
+    g = np.array([0.3, -2.0, 1e-3, 7.5])
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    step = -0.01 * g / (np.abs(g) + 1e-8)
+    for t in (1, 2, 3):
+        th, m, v = cnn.adam(th, m, v, g, t, lr=0.01)
+        assert np.allclose(th, t * step, rtol=1e-12, atol=0), t
+
+
+def test_adam_second_step_with_a_new_gradient():
+    """Two steps with gradients g1 then g2, against the moments written out for t = 2:
+    m = (1 - b1)(b1 g1 + g2), v = (1 - b2)(b2 g1^2 + g2^2), bias factors 1 - b^2."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.05, 1e-8
+    g1, g2 = np.array([0.5, -1.0, 2.0]), np.array([-0.25, -3.0, 2.0])
+    th, m, v = cnn.adam(np.zeros(3), np.zeros(3), np.zeros(3), g1, 1, lr=lr)
+    th, m, v = cnn.adam(th, m, v, g2, 2, lr=lr)
+    mh = (1 - b1) * (b1 * g1 + g2) / (1 - b1 ** 2)
+    vh = (1 - b2) * (b2 * g1 ** 2 + g2 ** 2) / (1 - b2 ** 2)
+    ref = -lr * g1 / (np.abs(g1) + eps) - lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(th, ref, rtol=1e-12, atol=1e-15)
+
+
+ADAM_MUTANTS = {
+    "first_bias_correction_fixed_at_t1": ("mh = m / (1 - b1 ** t)", "mh = m / (1 - b1)"),
+    "second_bias_correction_fixed_at_t1": ("vh = v / (1 - b2 ** t)", "vh = v / (1 - b2)"),
+    "no_square_root": ("np.sqrt(vh) + eps", "vh + eps"),
+    "first_moment_weights_swapped": ("m = b1 * m + (1 - b1) * g", "m = (1 - b1) * m + b1 * g"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ADAM_MUTANTS))
+def test_every_planted_adam_mistake_fails_a_pin(name, tmp_path):
+    import importlib.util
+    import os
+    global cnn
+    old, new = ADAM_MUTANTS[name]
+    src = open(os.path.join(os.path.dirname(cnn.__file__), "cnn.py")).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"cnn_{name}.py"
+    path.write_text(src.replace(old, new))
+    spec = importlib.util.spec_from_file_location(f"oracle.cnn_{name}", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    saved, failed = cnn, []
+    cnn = mod
+    try:
+        for pin in (test_adam_first_step_is_sign_step, test_adam_constant_gradient_takes_equal_steps,
+                    test_adam_second_step_with_a_new_gradient):
+            try:
+                pin()
+            except AssertionError:
+                failed.append(pin.__name__)
+    finally:
+        cnn = saved
+    assert failed, f"no pin catches the planted mistake {name!r}"

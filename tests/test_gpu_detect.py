@@ -55,8 +55,10 @@ def test_detect_matches_oracle(torch, G, rows, cols, looks, guard, train, radius
     J = _map(rows, cols, looks, rows * 1000 + cols, peaks)
     N = G.cfar_training_cells(guard, train)
     scale = G.cfar_scale(1e-6, N, looks)
+    scale_o = ocfar.scale_for_pfa(1e-6, N, looks)
+    assert abs(scale - scale_o) <= 1e-9 * scale_o
     log(f"detect {rows}x{cols} looks {looks} guard {guard} train {train} scale {scale:.3f}")
-    det_o = ocfar.detect(J.astype(np.float64), guard, train, scale, 16, radius)
+    det_o = ocfar.detect(J.astype(np.float64), guard, train, scale_o, 16, radius)
     with _plan(G, rows, cols) as plan:
         det_g = plan.detect(torch.from_numpy(J).cuda(), guard, train, scale, 16, radius)
     log(f"  {len(det_g[0])} detections: {list(det_g[0])}")

@@ -67,7 +67,7 @@ def test_proposal_workload_separate_captures(torch, G):
                                   [int(idx[0])], 31)
     log(f"  err_J = {e:.3g}")
     assert e <= DIRECT_TOL
-    assert Jo[np.searchsorted(sidx, int(idx[0]))] >= (1 - 2 * DIRECT_TOL) * np.max(Jo)
+    assert Jo[np.searchsorted(sidx, int(idx[0]))] >= (1 - DIRECT_TOL) * np.max(Jo)
 
 
 def test_continental_direct_and_caf(torch, G):
@@ -99,7 +99,7 @@ def test_continental_direct_and_caf(torch, G):
     for p in pk:
         near = np.array(_window(p, wl.n_rows, wl.n_cols, 3))
         sel = np.searchsorted(sidx, near)
-        assert Jo[np.searchsorted(sidx, int(p))] >= (1 - 2 * DIRECT_TOL) * np.max(Jo[sel])
+        assert Jo[np.searchsorted(sidx, int(p))] >= (1 - DIRECT_TOL) * np.max(Jo[sel])
 
     with G.Plan.for_scenario(scn, method=G.CAF_BF16) as cplan:
         t0 = time.time()
@@ -119,5 +119,5 @@ def test_continental_direct_and_caf(torch, G):
             mr, mc = sim.nearest_cell(scn.lat, scn.lon, *sim.mirror_latlon(wl, scn.lat[pr], scn.lon[pc]))
             if max(abs(r - pr), abs(c - pc)) <= 1 or max(abs(r - mr), abs(c - mc)) <= 1:
                 return True
-        return Jg[a] >= (1 - 2e-2) * Jg[int(pk[1])]
+        return Jg[a] >= (1 - 1e-2) * Jg[int(pk[1])]
     assert all(agrees(int(a)) for a in ck), (list(ck), list(pk))

@@ -61,7 +61,9 @@ def test_58_captures_find_the_four_emitters(torch):
         d = min((max(abs(r - pr), abs(c - pc)) for pr, pc in dcells), default=10 ** 9)
         assert d <= 2, ("CFAR missed", e.waveform, (r, c), dcells)
     Jd = Jg.reshape(wl.n_rows, wl.n_cols)
-    do = ocfar.detect(Jd, guard, train, scale, 16, 15)
+    scale_o = ocfar.scale_for_pfa(1e-6, (2 * train + 1) ** 2 - (2 * guard + 1) ** 2, len(snaps))
+    assert abs(scale - scale_o) <= 1e-9 * scale_o
+    do = ocfar.detect(Jd, guard, train, scale_o, 16, 15)
     assert [i for i, _, _ in do] == [int(p) for p in dk]
 
     rng = np.random.Generator(np.random.PCG64(33))

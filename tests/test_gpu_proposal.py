@@ -115,17 +115,21 @@ def test_refined_tiles_reproduce_the_full_map(torch, P):
                                                     "paper_2508_06672_amd", "weights", "proposal_cnn.npz")),
                     reason="no trained proposal weights in the tree")
 def test_trained_network_beats_coarse_map_tiles(torch, P):
-    """On held-out seeds the trained network's tiles contain the full map's peak (or a
-    tie of it) at least as often as the 16 best tiles of the coarse map itself."""
+    """On 100 held-out seeds the trained network's 16 tiles (no fallback: the tile choice
+    itself) find the full map's peak, by the agreement rule, strictly more often than the
+    16 best tiles of the coarse map itself: what the network adds to the method."""
     from paper_2508_06672_amd import geoloc
     theta, meta = P.load_weights()
     net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=64)
     net.set_params(theta)
     wl = P.TRAIN_WL
-    prop = P.Proposer(wl, net, threshold=0.0)           # no fallback: measure the tile choice itself
-    seeds = list(range(P.SEED_TEST, P.SEED_TEST + 24))
-    res = P.evaluate(prop, wl, seeds, None)
-    log(f"learned {res['learned']} ablation {res['coarse_top16_ablation']}")
-    assert res["learned"]["agree_rate"] >= res["coarse_top16_ablation"]["agree_rate"]
-    prop.close()
-    net.close()
+    prop = P.Proposer(wl, net, threshold=0.0)
+    seeds = list(range(P.SEED_TEST, P.SEED_TEST + 100))
+    try:
+        res = P.evaluate(prop, wl, seeds, None)
+    finally:
+        prop.close()
+        net.close()
+    L, A = res["learned"], res["coarse_top16_ablation"]
+    log(f"learned {L['agree_rate']:.3f} {L['rule']} | ablation {A['agree_rate']:.3f} {A['rule']}")
+    assert L["agree_rate"] > A["agree_rate"]

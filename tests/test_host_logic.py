@@ -1,6 +1,7 @@
 """Host-side logic that needs no GPU: separate captures (snapshots) of one scenario, and
 their layout as virtual receivers of one map call, for the proposal workload."""
 import numpy as np
+import pytest
 
 from oracle import subband as osub
 from paper_2508_06672_amd import configs, sim
@@ -54,3 +55,30 @@ def test_band_layout_matches_the_oracle_helpers():
     assert np.array_equal(P.band_states(st, 4), osub.states_for_bands(st, 4))
     pr = [(0, 1), (2, 3), (4, 5)]
     assert P.band_pairs(pr, 6, 4) == osub.pairs_for_bands(pr, 6, 4)
+
+
+def test_agreement_margin_and_classes():
+    """The peak-agreement rule on a hand-made map: the margin excludes the 3 x 3 cells around
+    the peak and around its mirror; well-conditioned at margin > 2 eps; within one cell of
+    either; eps-optimal on the reference values."""
+    from paper_2508_06672_amd import agreement as A
+    n_rows, n_cols = 20, 30
+    J = np.ones((n_rows, n_cols))
+    J[5, 7] = 10.0                 # peak
+    J[6, 8] = 9.99                 # inside N1(peak): ignored by the margin
+    J[14, 7] = 9.995               # the mirror twin
+    J[2, 25] = 9.0                 # best value outside both neighbourhoods
+    a, mirror = 5 * n_cols + 7, 14 * n_cols + 7
+    Jf = J.ravel()
+    assert A.margin(Jf, n_cols, a, mirror) == pytest.approx(0.1)
+    assert A.margin(Jf, n_cols, a) == pytest.approx(0.0005)       # without the mirror it is a near-tie
+    c = A.classify(Jf, n_cols, mirror + 1, a, 1e-2, mirror)
+    assert c["well_conditioned"] and c["within_one"] and c["cell_dist"] == 1 and c["eps_optimal"] is False
+    c = A.classify(Jf, n_cols, 2 * n_cols + 25, a, 0.06, mirror)
+    assert not c["well_conditioned"] and not c["within_one"] and not c["eps_optimal"]
+    c = A.classify(Jf, n_cols, 2 * n_cols + 25, a, 0.1, mirror)
+    assert c["eps_optimal"] and not c["well_conditioned"]
+    s = A.summarise([A.classify(Jf, n_cols, a, a, 1e-2, mirror), A.classify(Jf, n_cols, 0, a, 1e-2, mirror)], 1e-2)
+    assert s["n_scenarios"] == 2 and s["well_conditioned_fraction"] == 1.0
+    assert s["within_one_cell_well_conditioned"] == 0.5 and s["eps_optimal_all"] == 0.5
+    assert A.cell_dist(0, n_cols * 3 + 2, n_cols) == 3
