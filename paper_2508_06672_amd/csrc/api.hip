@@ -46,7 +46,7 @@ namespace {
     } while (0)
 
 constexpr uint32_t kMagic = 0x67656f6cu;  // "geol"
-constexpr int64_t kGeomChunkBytes = 512ll << 20;
+constexpr int64_t kMaskChunkBytes = 64ll << 20;  // deferral mask of one correlation launch
 constexpr int32_t kMaxShear = 4 * kShearOne;   // steepest tile shear: 4 columns per row
 
 struct TimedSpan {
@@ -68,7 +68,6 @@ struct geoloc_plan_s {
     PointTiling base_tiling{};       // 16 x 16 squares (RECT; CAF and per-point paths) or runs of 256 points (POINTS)
     std::vector<PointTiling> tile_shapes;   // RECT: candidate tilings of the factored kernel
     int64_t max_tiles = 0;           // most tiles of any candidate (scratch is sized for it)
-    int64_t max_table = 0;           // most tile-major table entries (tiles x cells) of any candidate
     bool tiling_fixed = false;       // geoloc_set_tiling: use fixed_tiling instead of the per-map choice
     int32_t* d_tiles = nullptr;      // geoloc_set_points_from_tiles: the tile list
     int32_t d_tiles_cap = 0;
@@ -77,15 +76,15 @@ struct geoloc_plan_s {
     std::vector<double> h_alt;              // per-point terrain height (host copy), empty if none
     int32_t earth_model = GEOLOC_EARTH_SPHERE;
     double* d_alt = nullptr;         // [P] per-point terrain height, or null
-    int32_t kc = 1;  // steps per geometry chunk
+    int32_t kc = 1;  // steps per correlation launch
     // device scratch
     double* d_xyz = nullptr;
     double* d_lat = nullptr;         // grid coordinates as given (kept for geoloc_set_grid)
     double* d_lon = nullptr;
     double* d_states = nullptr;
     int2* d_pairs = nullptr;
-    double* d_D = nullptr;
-    double* d_nu = nullptr;
+    uint32_t* d_defer_flags = nullptr;   // [step chunks] deferral flag of each correlation launch
+    uint32_t defer_seq = 0;              // sequence number of the current map (never 0)
     double* d_partial = nullptr;     // [item groups][P] when a plan's grid is too small to fill the GPU
     int32_t n_groups = 1;
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
@@ -173,8 +172,7 @@ void release(geoloc_plan_t p) {
     (void)hipFree(p->d_lon);
     (void)hipFree(p->d_states);
     (void)hipFree(p->d_pairs);
-    (void)hipFree(p->d_D);
-    (void)hipFree(p->d_nu);
+    (void)hipFree(p->d_defer_flags);
     (void)hipFree(p->d_partial);
     (void)hipFree(p->d_cpart);
     (void)hipFree(p->d_sat);
@@ -483,10 +481,8 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
 }
 
 int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc, double* D, double* nu,
-                 bool tile_major, hipStream_t s) {
+                 hipStream_t s) {
     GeomArgs g{};
-    g.tiling = p->tiling;
-    g.tile_major = tile_major ? 1 : 0;
     g.xyz = p->d_xyz;
     g.states = p->d_states;
     g.pairs = p->d_pairs + pair_lo;
@@ -882,7 +878,6 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
                         c.shear = sg * kMaxShear;
                         tiling_counts(c);
                         p->max_tiles = std::max(p->max_tiles, c.tiles_x * c.tiles_y);
-                        p->max_table = std::max(p->max_table, c.tiles_x * c.tiles_y * tile_lanes(c));
                     }
                 }
         }
@@ -890,9 +885,10 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         p->h_lon.assign(d->lon, d->lon + (d->grid_kind == GEOLOC_GRID_RECT ? d->n_cols : P));
     }
 
-    const int64_t table_points = std::max(p->max_table, p->base_tiling.tiles_x * p->base_tiling.tiles_y * kTilePoints);
-    const int64_t per_step = (int64_t)p->n_pairs * table_points * 16;
-    int64_t kc = kGeomChunkBytes / per_step;
+    // steps per correlation launch: all of them, unless the deferral mask of one launch
+    // ([pairs][steps][tiles] bytes) would exceed its budget
+    const int64_t per_step = (int64_t)p->n_pairs * std::max<int64_t>(p->max_tiles, 1);
+    int64_t kc = kMaskChunkBytes / per_step;
     if (kc < 1) kc = 1;
     if (kc > p->K) kc = p->K;
     const int64_t n_chunks = (p->K + kc - 1) / kc;
@@ -902,8 +898,11 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if ((rc = dev_alloc(p, &p->d_xyz, (size_t)P * 3))) break;
         if ((rc = dev_alloc(p, &p->d_states, (size_t)p->K * p->n_rx * 6))) break;
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
-        if ((rc = dev_alloc(p, &p->d_D, (size_t)p->n_pairs * p->kc * table_points))) break;
-        if ((rc = dev_alloc(p, &p->d_nu, (size_t)p->n_pairs * p->kc * table_points))) break;
+        if ((rc = dev_alloc(p, &p->d_defer_flags, (size_t)n_chunks))) break;
+        if (hipMemset(p->d_defer_flags, 0, (size_t)n_chunks * sizeof(uint32_t)) != hipSuccess) {
+            rc = fail(GEOLOC_ELAUNCH, "hipMemset failed");
+            break;
+        }
         p->use_fact = p->method == GEOLOC_DIRECT_FP32;
         const int64_t base_tiles = p->base_tiling.tiles_x * p->base_tiling.tiles_y;
         const int64_t items = (int64_t)p->kc * p->n_pairs;
@@ -1037,7 +1036,7 @@ int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t s
     t.shear = shear;
     t.transpose = transpose;
     tiling_counts(t);
-    if (t.tiles_x * t.tiles_y > p->max_tiles || t.tiles_x * t.tiles_y * cells > p->max_table)
+    if (t.tiles_x * t.tiles_y > p->max_tiles)
         return fail(GEOLOC_EINVAL, "tiling exceeds the plan's scratch");
     p->fixed_tiling = t;
     p->tiling_fixed = true;
@@ -1079,17 +1078,19 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         if (p->timing) p->timed_maps++;
         return GEOLOC_OK;
     }
+    // a new sequence number per map: a deferral flag holds it only if this map's factored
+    // launch deferred something (0 is the flags' initial value, never a sequence number)
+    if (++p->defer_seq == 0) p->defer_seq = 1;
     for (int64_t k0 = 0; k0 < p->K; k0 += p->kc) {
         const int32_t kc = (int32_t)std::min<int64_t>(p->kc, p->K - k0);
-        TimedSpan sg{}, sc{};
-        if ((rc = span_begin(p, s, &sg, 0))) return rc;
-        if ((rc = run_geometry(p, 0, p->n_pairs, k0, kc, p->d_D, p->d_nu, true, s))) return rc;
-        if ((rc = span_end(p, s, &sg))) return rc;
-
+        TimedSpan sc{};
         DirectArgs a{};
         a.cap = (const float2*)in->captures;
-        a.D = p->d_D;
-        a.nu = p->d_nu;
+        a.xyz = p->d_xyz;
+        a.states = p->d_states;
+        a.n_rx = p->n_rx;
+        a.fs = p->fs;
+        a.inv_lambda = p->fc / kLightSpeed;
         a.pairs = p->d_pairs;
         a.J = J;
         a.tiling = p->tiling;
@@ -1109,6 +1110,8 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.n_segs = p->use_fact ? p->n_segs : 1;
         a.seg_len = p->seg_len;
         a.cpart = p->d_cpart;
+        a.defer_flag = p->d_defer_flags + k0 / p->kc;
+        a.defer_seq = p->defer_seq;
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
         if (p->use_fact) {
             HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, p->fact_wide, p->fact_sub, s));
@@ -1154,7 +1157,7 @@ int geoloc_geometry(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index
     hipStream_t s = (hipStream_t)in->stream;
     int rc = upload_states(p, in->rx_state, s);
     if (rc) return rc;
-    return run_geometry(p, pair_index, 1, step_lo, (int32_t)n_steps, D, nu, false, s);
+    return run_geometry(p, pair_index, 1, step_lo, (int32_t)n_steps, D, nu, s);
 }
 
 int geoloc_caf_table(geoloc_plan_t p, const geoloc_inputs* in, int32_t pair_index, int64_t step_lo, int64_t n_steps,

@@ -67,12 +67,15 @@ __host__ __device__ inline int64_t tile_point(const PointTiling& t, int64_t tile
 
 struct DirectArgs {
     const float2* cap;       // [n_rx][N] complex64
-    const double* D;         // delay in samples, tile-major (see n_tiles)
-    const double* nu;        // FDOA in Hz, tile-major
+    // geometry, evaluated inline per (point, step, pair) in FP64 (Eq. (3)-(9))
+    const double* xyz;       // [P][3] ECEF of the grid points
+    const double* states;    // [K][n_rx][6] receiver position and velocity per step
+    int32_t n_rx;
+    double fs, inv_lambda;
     const int2* pairs;       // [n_pairs]
     float* J;                // [P]
     PointTiling tiling;
-    int64_t n_tiles;         // tiles_x * tiles_y; D / nu are [n_pairs][kc][n_tiles][tile lanes]
+    int64_t n_tiles;         // tiles_x * tiles_y
     int64_t N, P;
     int32_t L, k0, kc, n_pairs;
     double inv_fs;
@@ -81,6 +84,12 @@ struct DirectArgs {
     int32_t n_groups;        // groups of (pair, step) items per chunk (1: each workgroup owns its points' J)
     double* partial;         // [n_groups][P] partial sums when n_groups > 1
     const uint8_t* mask;     // [n_pairs][kc][n_tiles]: nonzero = this kernel handles it; NULL = all
+    // deferral flag of this launch: the factored kernel stores defer_seq into *defer_flag
+    // when it leaves any (tile, step) to the per-point kernel, whose masked pass returns at
+    // once unless the flag holds defer_seq (a per-map sequence number, so the flag never
+    // needs clearing)
+    uint32_t* defer_flag;
+    uint32_t defer_seq;
     // factored kernel only: each step split into n_segs coherent segments of seg_len samples
     // (a multiple of 64) whose complex sums go to cpart [n_segs][n_pairs * kc][P]; 1 = off
     int32_t n_segs, seg_len;
@@ -151,10 +160,8 @@ struct GeomArgs {
     const double* xyz;       // [P][3]
     const double* states;    // [K][n_rx][6]
     const int2* pairs;
-    double* D;               // [n_pairs][kc][P], or tile-major [n_pairs][kc][n_tiles][256]
+    double* D;               // [n_pairs][kc][P]
     double* nu;
-    PointTiling tiling;
-    int32_t tile_major;      // write the tile-major layout read by the correlation kernels
     int64_t P;
     int32_t n_rx, n_pairs, k0, kc;
     double fs, inv_lambda;
@@ -172,6 +179,19 @@ __device__ inline void delay_doppler(double q0, double q1, double q2, const doub
     *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
 }
 
+// TDOA in samples and FDOA in Hz of the receiver pair pr at ECEF point q and step k
+// (Eq. (7)-(9)) from the states [K][n_rx][6]. Every kernel that needs the geometry of a
+// (point, step, pair) evaluates it through this function, so they all see the same values.
+__device__ inline void pair_geometry(double q0, double q1, double q2, const double* __restrict__ states, int32_t n_rx,
+                                     int32_t k, int2 pr, double fs, double inv_lambda, double* D, double* nu) {
+#pragma clang fp contract(off)
+    double ti, fi, tj, fj;
+    delay_doppler(q0, q1, q2, states + ((int64_t)k * n_rx + pr.x) * 6, inv_lambda, &ti, &fi);
+    delay_doppler(q0, q1, q2, states + ((int64_t)k * n_rx + pr.y) * 6, inv_lambda, &tj, &fj);
+    *D = (tj - ti) * fs;
+    *nu = fj - fi;
+}
+
 // Everything the CAF kernels need to evaluate the geometry of (point, step, pair) inline.
 struct CafGeomArgs {
     const double* xyz;       // [P][3]
@@ -186,13 +206,8 @@ struct CafGeomArgs {
 __device__ inline void pair_delay_doppler(const CafGeomArgs& g, int64_t p, int32_t k, int32_t e, double* D,
                                           double* nu) {
 #pragma clang fp contract(off)
-    const int2 pr = g.pairs[e];
-    const double q0 = g.xyz[3 * p], q1 = g.xyz[3 * p + 1], q2 = g.xyz[3 * p + 2];
-    double ti, fi, tj, fj;
-    delay_doppler(q0, q1, q2, g.states + ((int64_t)k * g.n_rx + pr.x) * 6, g.inv_lambda, &ti, &fi);
-    delay_doppler(q0, q1, q2, g.states + ((int64_t)k * g.n_rx + pr.y) * 6, g.inv_lambda, &tj, &fj);
-    *D = (tj - ti) * g.fs;
-    *nu = fj - fi;
+    pair_geometry(g.xyz[3 * p], g.xyz[3 * p + 1], g.xyz[3 * p + 2], g.states, g.n_rx, k, g.pairs[e], g.fs,
+                  g.inv_lambda, D, nu);
 }
 
 // CAF GEMM workgroup tile: table rows (lags) x columns (Doppler bins); the table is padded
@@ -244,6 +259,7 @@ struct ArgmaxScratch {
     int32_t n_blocks = 0;
 };
 constexpr int kMaxTopK = 64;
+constexpr int kArgmaxMaxBlocks = 1024;   // most block partials of one argmax pass
 hipError_t launch_argmax(const float* J, int64_t P, int64_t cols, int32_t rect, int32_t radius, int32_t top_k,
                          ArgmaxScratch& s, hipStream_t st);
 // Record a detail string for geoloc_last_error() and return code.

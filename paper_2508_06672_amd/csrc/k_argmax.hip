@@ -13,12 +13,11 @@
 namespace geoloc {
 
 constexpr int kArgThreads = 256;
-constexpr int kArgMaxBlocks = 1024;
 
 int32_t argmax_blocks(int64_t P) {
     int64_t b = (P + 4 * kArgThreads - 1) / (4 * kArgThreads);
     if (b < 1) b = 1;
-    if (b > kArgMaxBlocks) b = kArgMaxBlocks;
+    if (b > kArgmaxMaxBlocks) b = kArgmaxMaxBlocks;
     return (int32_t)b;
 }
 

@@ -2,7 +2,7 @@
 // the non-coherent sum over steps and pairs of Algorithm 1 fused in.
 //
 // Per candidate point p, step k and pair (i, j), with D = d0 + a and FDOA nu from the
-// FP64 geometry table:
+// FP64 geometry (Eq. (3)-(9), evaluated inline per point and step):
 //   C = sum_{n in step k} y_i[n] conj(yt_j[n]) exp(+j 2 pi nu t_n),  t_n from the step centre
 //   yt_j[n] = y_j[n+d0] + a (y_j[n+d0+1] - y_j[n+d0])   (LINEAR; ROUND uses y_j[n+round(D)])
 //   J(p) += |C|^2  (or |C|).
@@ -11,8 +11,6 @@
 //  * one workgroup = 256 candidate points (a tile of a rectilinear grid, or one half of a 512-cell tile),
 //    one point per lane; a point owns its J value for the whole launch, so the sums
 //    over steps and pairs need no atomics and are deterministic;
-//  * the FP64 geometry table is stored tile-major, so each workgroup reads one aligned,
-//    contiguous 2 KiB run of delays and one of FDOAs per step;
 //  * per step the tile's lag range [dlo, dhi] is found by a wave-shuffle + LDS
 //    reduction; a sample tile of y_j[n0+dlo .. n0+T+dhi] (zero outside the capture) is
 //    staged through LDS with coalesced loads and every lane reads its own delayed taps
@@ -134,6 +132,8 @@ void k_direct(DirectArgs a) {
     // chunk's (pair, step) items, pair-major, into its own partial row, reduced afterwards
     // in a fixed order
     // (a tile of 512 cells is two workgroups, one per half)
+    // a masked pass after a factored launch that deferred nothing has nothing to add
+    if (a.mask && *a.defer_flag != a.defer_seq) return;
     const int halves = tile_lanes(a.tiling) / 256;
     const int64_t sub = blockIdx.x % (a.n_tiles * halves);
     const int64_t tile = sub / halves;
@@ -160,9 +160,11 @@ void k_direct(DirectArgs a) {
             // with a mask, only the (tile, step) pairs the factored kernel left over
             if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-            const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * (halves * 256) + lane;
-            double D = valid ? a.D[gi] : 0.0;
-            const double nu = valid ? a.nu[gi] : 0.0;
+            // delay (samples) and Doppler shift (Hz) of this point, Eq. (3)-(9) in FP64
+            double D = 0.0, nu = 0.0;
+            if (valid)
+                pair_geometry(a.xyz[3 * p], a.xyz[3 * p + 1], a.xyz[3 * p + 2], a.states, a.n_rx, a.k0 + kk, pr, a.fs,
+                              a.inv_lambda, &D, &nu);
             // keep the integer lag representable whatever the geometry (NaN included);
             // such a lag lies outside any capture and reads zeros
             if (!(fabs(D) < 1.0e9)) D = 1.0e9;

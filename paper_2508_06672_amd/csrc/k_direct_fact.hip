@@ -330,7 +330,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
     __shared__ float2 s_rot[kLB];
     __shared__ int s_i[2][4];
     __shared__ float s_f[2][4];
-    constexpr int kLanes = 256 * kPPT;
 
     const int tid = threadIdx.x;
     // workgroup -> (point tile, group of (pair, step) items, segment of the step)
@@ -358,31 +357,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
             if (valid[k]) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p[k]] = make_float2(0.f, 0.f);
     };
 
-    // this item's delays and Doppler shifts, loaded one item ahead (item it is entry
-    // it * n_tiles + tile of the tile-major table, it = e * kc + kk)
-    double nD[kPPT], nnu[kPPT];
-    auto fetch = [&](int64_t it) {
+    // ECEF of this thread's points (an invalid lane takes point 0's, whose values it never
+    // uses), for the FP64 geometry of every item
+    double qx[kPPT], qy[kPPT], qz[kPPT];
 #pragma unroll
-        for (int k = 0; k < kPPT; ++k) {
-            const int64_t gi = (it * a.n_tiles + tile) * kLanes + tid + 256 * k;
-            nD[k] = (valid[k] && it < it_hi) ? a.D[gi] : 0.0;
-            nnu[k] = (valid[k] && it < it_hi) ? a.nu[gi] : 0.0;
-        }
-    };
-    fetch(it_lo);
+    for (int k = 0; k < kPPT; ++k) {
+        qx[k] = a.xyz[3 * p[k]];
+        qy[k] = a.xyz[3 * p[k] + 1];
+        qz[k] = a.xyz[3 * p[k] + 2];
+    }
     for (int64_t it = it_lo; it < it_hi; ++it) {
         const int e = (int)(it / a.kc);
         const int kk = (int)(it - (int64_t)e * a.kc);
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
+        // this item's delays (samples) and Doppler shifts (Hz), Eq. (3)-(9) in FP64
         double cD[kPPT], cnu[kPPT];
 #pragma unroll
-        for (int k = 0; k < kPPT; ++k) {
-            cD[k] = nD[k];
-            cnu[k] = nnu[k];
-        }
-        fetch(it + 1);
+        for (int k = 0; k < kPPT; ++k)
+            pair_geometry(qx[k], qy[k], qz[k], a.states, a.n_rx, a.k0 + kk, pr, a.fs, a.inv_lambda, &cD[k], &cnu[k]);
         FactPoint pt[kPPT];
         int d0[kPPT];
         float th[kPPT];
@@ -436,7 +430,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         constexpr int kTaps = kMode == GEOLOC_DELAY_SINC ? kSincTaps : 2;
         constexpr int kTapLo = kMode == GEOLOC_DELAY_SINC ? kSincLo : 0;
         const bool fact = Q > 0 && spread + kTaps <= kFH;
-        if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
+        if (tid == 0 && seg == 0) {
+            deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
+            if (!fact) *a.defer_flag = a.defer_seq;
+        }
         if (!fact) {                                   // uniform: the per-point kernel takes it
             zero_cpart(it);
             continue;

@@ -17,6 +17,8 @@ constexpr int kSincAnchor = 64;   // samples between FP64 phase re-anchors
 __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
     const int tid = threadIdx.x;
     // (a tile of 512 cells is two workgroups, one per half)
+    // a masked pass after a factored launch that deferred nothing has nothing to add
+    if (a.mask && *a.defer_flag != a.defer_seq) return;
     const int halves = tile_lanes(a.tiling) / 256;
     const int64_t sub = blockIdx.x % (a.n_tiles * halves);
     const int64_t tile = sub / halves;
@@ -42,9 +44,10 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
-        const int64_t gi = (((int64_t)e * a.kc + kk) * a.n_tiles + tile) * (halves * 256) + lane;
-        double D = a.D[gi];
-        const double nu = a.nu[gi];
+        // delay (samples) and Doppler shift (Hz) of this point, Eq. (3)-(9) in FP64
+        double D, nu;
+        pair_geometry(a.xyz[3 * p], a.xyz[3 * p + 1], a.xyz[3 * p + 2], a.states, a.n_rx, a.k0 + kk, pr, a.fs,
+                      a.inv_lambda, &D, &nu);
         if (!(fabs(D) < 1.0e9)) D = 1.0e9;
         const double f = floor(D);
         const int64_t d0 = (int64_t)f;

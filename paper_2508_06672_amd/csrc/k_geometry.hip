@@ -79,37 +79,21 @@ hipError_t launch_tile_points(const double* glat, const double* glon, int64_t ro
     return hipGetLastError();
 }
 
-// One thread per (pair, step, point). Point order: idx = (e * kc + kk) * P + p.
-// Tile-major order: idx = ((e * kc + kk) * n_tiles + tile) * lanes + lane, with the point of
-// (tile, lane) as in the correlation kernels; lanes past the grid edge write zeros.
+// One thread per (pair, step, point), idx = (e * kc + kk) * P + p: the geometry alone, for
+// geoloc_geometry (the correlation kernels evaluate the same function inline).
 __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t lanes = tile_lanes(a.tiling);
-    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * lanes : a.P;
-    const int64_t total = per_step * a.kc * a.n_pairs;
+    const int64_t total = a.P * a.kc * a.n_pairs;
     if (idx >= total) return;
-    const int64_t within = idx % per_step;
-    const int64_t rest = idx / per_step;
+    const int64_t p = idx % a.P;
+    const int64_t rest = idx / a.P;
     const int32_t kk = (int32_t)(rest % a.kc);
     const int32_t e = (int32_t)(rest / a.kc);
-    int64_t p = within;
-    if (a.tile_major) {
-        bool valid;
-        p = tile_point(a.tiling, within / lanes, (int)(within % lanes), &valid);
-        if (!valid) {
-            a.D[idx] = 0.0;
-            a.nu[idx] = 0.0;
-            return;
-        }
-    }
-    int32_t k = a.k0 + kk;
-    int2 pr = a.pairs[e];
-    double q0 = a.xyz[3 * p], q1 = a.xyz[3 * p + 1], q2 = a.xyz[3 * p + 2];
-    double ti, fi, tj, fj;
-    delay_doppler(q0, q1, q2, a.states + ((int64_t)k * a.n_rx + pr.x) * 6, a.inv_lambda, &ti, &fi);
-    delay_doppler(q0, q1, q2, a.states + ((int64_t)k * a.n_rx + pr.y) * 6, a.inv_lambda, &tj, &fj);
-    a.D[idx] = (tj - ti) * a.fs;
-    a.nu[idx] = fj - fi;
+    double D, nu;
+    pair_geometry(a.xyz[3 * p], a.xyz[3 * p + 1], a.xyz[3 * p + 2], a.states, a.n_rx, a.k0 + kk, a.pairs[e], a.fs,
+                  a.inv_lambda, &D, &nu);
+    a.D[idx] = D;
+    a.nu[idx] = nu;
 }
 
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
@@ -123,9 +107,7 @@ hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_k
 }
 
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s) {
-    const int64_t lanes = tile_lanes(a.tiling);
-    const int64_t per_step = a.tile_major ? a.tiling.tiles_x * a.tiling.tiles_y * lanes : a.P;
-    const int64_t total = per_step * a.kc * a.n_pairs;
+    const int64_t total = a.P * a.kc * a.n_pairs;
     dim3 grid((unsigned)((total + 255) / 256));
     hipLaunchKernelGGL(k_geometry, grid, dim3(256), 0, s, a);
     return hipGetLastError();
