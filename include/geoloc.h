@@ -266,6 +266,21 @@ int geoloc_caf_table(geoloc_plan_t plan, const geoloc_inputs* in, int32_t pair_i
 int geoloc_argmax(geoloc_plan_t plan, const float* J_dev, int32_t top_k, int32_t nms_radius_cells,
                   int64_t* idx_host, float* val_host, void* stream);
 
+/* geoloc_argmax without a plan and without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, hosts that forbid hipMalloc).
+ * Same peaks, order, window and errors as geoloc_argmax on a plan with the same grid:
+ * J_dev is the caller's float32 DEVICE map of n_rows * n_cols points (grid_kind RECT: rows =
+ * latitude; POINTS: any n_rows x n_cols = P), idx_host / val_host HOST arrays of top_k.
+ * Its scratch (block partials and the peaks found so far, 13 KB) is one static device
+ * array per GPU, held until the process ends; it is looked up on the first call on each
+ * device (which must be current) and needs no clearing. Calls that overlap on one GPU
+ * (other threads or streams) race on that array: serialise them. Synchronises `stream`.
+ * Errors: EINVAL (NULL pointer, unknown grid kind, empty grid, top_k outside [1, 64]: the
+ * array holds 64 peaks, r < 0, r > 0 on a POINTS grid), ENAN, EDEVICE (no gfx950 device
+ * current), ELAUNCH. */
+int geoloc_argmax_noalloc(const float* J_dev, int32_t grid_kind, int64_t n_rows, int64_t n_cols, int32_t top_k,
+                          int32_t nms_radius_cells, int64_t* idx_host, float* val_host, void* stream);
+
 /* Threshold detection of several emitters (the threshold step of Algorithm 1, which the
  * paper leaves open), read as cell-averaging CFAR on a RECT map J_dev[rows][cols]: the noise
  * level of a cell is the mean of J over the cells within Chebyshev distance train_cells of

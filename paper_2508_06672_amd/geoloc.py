@@ -114,9 +114,11 @@ def load() -> ctypes.CDLL:
     lib.geoloc_last_error.restype = ctypes.c_char_p
     lib.geoloc_subbands.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     lib.geoloc_cfar_scale.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
+    lib.geoloc_argmax_noalloc.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
                  "geoloc_detect", "geoloc_set_tiling", "geoloc_set_taylor_block", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
-                 "geoloc_subbands", "geoloc_cfar_scale"):
+                 "geoloc_subbands", "geoloc_cfar_scale", "geoloc_argmax_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -198,6 +200,17 @@ def geoloc_argmax(plan: int, J_dev: int, top_k: int, nms_radius: int, stream: in
     _check(load().geoloc_argmax(plan, J_dev, top_k, nms_radius,
                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream), "geoloc_argmax")
+    return idx, val
+
+
+def geoloc_argmax_noalloc(J_dev: int, grid_kind: int, n_rows: int, n_cols: int, top_k: int, nms_radius: int,
+                          stream: int) -> Tuple[np.ndarray, np.ndarray]:
+    idx = np.empty(top_k, dtype=np.int64)
+    val = np.empty(top_k, dtype=np.float32)
+    _check(load().geoloc_argmax_noalloc(J_dev, grid_kind, n_rows, n_cols, top_k, nms_radius,
+                                        idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        val.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream),
+           "geoloc_argmax_noalloc")
     return idx, val
 
 
