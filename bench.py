@@ -309,6 +309,15 @@ def agreement(geoloc, torch, wl, seeds, pool, eps: float = CAF_EPS, out_path=Non
                                               "err_vs_direct": r[m]["err_vs_direct"],
                                               "cell_dist": r[m]["cell_dist"]} for r in miss]
         out[m]["max_err_vs_direct"] = max(r[m]["err_vs_direct"] for r in recs)
+        # the same cell rule at the map error each scenario actually has: where the direct
+        # map's margin exceeds twice the CAF map's measured error on that scenario, no error
+        # of that size can move the peak out of the 3 x 3 cells of the direct peak
+        sure = [r for r in recs if r[m]["margin"] > 2 * r[m]["err_vs_direct"]]
+        out[m]["margin_above_2_err"] = {"n": len(sure), "within_one_cell": (sum(r[m]["within_one"] for r in sure) /
+                                                                            len(sure)) if sure else None}
+    mg = np.array([r["bf16"]["margin"] for r in recs])
+    out["direct_margin_quantiles"] = {q: float(np.quantile(mg, v)) for q, v in
+                                      (("min", 0.0), ("median", 0.5), ("p90", 0.9), ("max", 1.0))}
     if out_path:
         with open(out_path, "w") as fh:
             json.dump({"summary": out, "records": recs}, fh)
@@ -349,16 +358,17 @@ def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
     return {"batch": batch, "ms": ms, "samples_per_s": batch / (ms / 1e3), "params": int(theta.size)}
 
 
-def learned_leg(geoloc, seeds, pool=None, out_path=None):
+def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bool = True):
     """The learned tile proposal with its stored weights and calibrated fallback on held-out
-    proposal scenarios: median time against the full plain map of the same scenario, and
-    how often its argmax agrees with the full map's (within one cell, on the orbital-plane
-    mirror, or tol-optimal), beside the coarse-map top-16 ablation."""
+    proposal scenarios (the training workload unless wl is given): median time against the
+    full plain map of the same scenario, and how often its argmax agrees with the full
+    map's (within one cell, on the orbital-plane mirror, or tol-optimal), beside the
+    coarse-map top-16 ablation."""
     from paper_2508_06672_amd import proposal as P
     theta, meta = P.load_weights()
     net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=1)
     net.set_params(theta)
-    wl = P.TRAIN_WL
+    wl = wl or P.TRAIN_WL
     prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"))
     try:
         res = P.evaluate(prop, wl, seeds, pool)
@@ -369,7 +379,7 @@ def learned_leg(geoloc, seeds, pool=None, out_path=None):
         with open(out_path, "w") as fh:
             json.dump(res, fh)
     L, A = res["learned"], res["coarse_top16_ablation"]
-    train = train_step_leg(geoloc, theta)
+    train = train_step_leg(geoloc, theta) if train_step else None
     return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"], "train_step": train,
             "threshold": meta["threshold"], "n_train": meta.get("n_train"), "params": int(theta.size),
             "full_map_median_ms": res["full_map_median_ms"],
@@ -549,10 +559,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-caf", action="store_true", help="skip the CAF-table legs")
-    ap.add_argument("--agreement-seeds", type=int, default=200,
+    ap.add_argument("--agreement-seeds", type=int, default=1000,
                     help="scenarios (seeds 10000..) for the CAF-vs-direct argmax agreement (0 skips it)")
-    ap.add_argument("--proposal-seeds", type=int, default=100,
+    ap.add_argument("--proposal-seeds", type=int, default=300,
                     help="held-out scenarios (seeds 1030000..) for the learned-proposal leg (0 skips it)")
+    ap.add_argument("--c4-seeds", type=int, default=200,
+                    help="held-out scenarios (seeds 1030000..) of the single-capture 100 ms workload on which the "
+                         "learned proposal (trained on the 10-capture workload) is also evaluated (0 skips it)")
     ap.add_argument("--study", action="store_true",
                     help="the full agreement study: 1000 CAF seeds and 300 learned-proposal seeds, with "
                          "per-scenario records written under --study-out")
@@ -573,8 +586,9 @@ def main() -> int:
 
     if args.study:
         args.agreement_seeds, args.proposal_seeds = max(args.agreement_seeds, 1000), max(args.proposal_seeds, 300)
+        args.c4_seeds = max(args.c4_seeds, 300)
     pool = None
-    if args.agreement_seeds > 0 or args.proposal_seeds > 0:
+    if args.agreement_seeds > 0 or args.proposal_seeds > 0 or args.c4_seeds > 0:
         # simulator workers are forked before anything touches the GPU
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(max(1, min(args.workers, len(os.sched_getaffinity(0)))))
@@ -682,6 +696,14 @@ def main() -> int:
         learned = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.proposal_seeds)), pool,
                               out_path=os.path.join(rec_dir, "agreement_learned.json") if rec_dir else None)
 
+    learned_c4 = None
+    if args.c4_seeds > 0:
+        from paper_2508_06672_amd import proposal as P
+        log(f"learned proposal on the single-capture workload over {args.c4_seeds} held-out scenarios")
+        learned_c4 = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.c4_seeds)), pool,
+                                 out_path=os.path.join(rec_dir, "agreement_learned_c4.json") if rec_dir else None,
+                                 wl=configs.PROPOSAL_C4, train_step=False)
+
     paper = None
     if not args.no_paper_scenario:
         log("58-capture scenario")
@@ -716,6 +738,7 @@ def main() -> int:
         "caf": caf,
         "delay_modes": modes,
         "learned": learned,
+        "learned_single_capture": learned_c4,
         "paper_scenario": paper,
         "continental": continental,
     }

@@ -100,6 +100,15 @@ PROPOSAL = MAP_1E6.with_(
     snr_db=-10.0, snr_db_range=(-20.0, 0.0),
     n_samples=100_000, step_len=100_000, n_snapshots=10, snapshot_spacing_s=4.0,
 )
+# The learned-proposal workload exactly as first specified: one contiguous 100 ms capture of
+# the 1e6-point map's kind (100 coherent steps of 1 ms) on the 1024 x 1024 grid. Its map is a
+# delay ridge whose maximum along the ridge is set by the noise, so it is evaluated beside
+# PROPOSAL (whose network was trained on PROPOSAL), not trained on.
+PROPOSAL_C4 = MAP_1E6.with_(
+    name="proposal_c4_1024x1024_10MHz_1x100ms",
+    n_rows=1024, n_cols=1024, waveform="tone|chirp|gauss",
+    snr_db=-10.0, snr_db_range=(-20.0, 0.0),
+)
 PROPOSAL_COARSE = 64
 PROPOSAL_TILE = 16
 PROPOSAL_TOPK = 16
