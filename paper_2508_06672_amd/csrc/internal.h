@@ -142,6 +142,8 @@ __device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
 }
 
 // sub_blocks: 64-sample sub-blocks per Taylor block, 1 or 4
+// Workgroups of the factored kernel resident per CU for this launch's variant.
+int32_t fact_wgs_per_cu(const DirectArgs& a, int32_t delay_mode, bool wide_doppler, int32_t sub_blocks);
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
@@ -266,7 +268,7 @@ hipError_t launch_argmax(const float* J, int64_t P, int64_t cols, int32_t rect, 
 int set_last_error(int code, const char* msg);
 int32_t argmax_blocks(int64_t P);
 
-int32_t caf_extent_blocks(int64_t total);
+int32_t caf_extent_blocks(int64_t points);
 hipError_t launch_caf_extent(const CafGeomArgs& a, double* part, int32_t blocks, hipStream_t s);
 hipError_t launch_caf_power(const float2* cap, int64_t N, int32_t n_rx, double* part, int32_t blocks, hipStream_t s);
 hipError_t launch_caf_phasor(bool f16, int32_t L_pad, int32_t L, int32_t M, int32_t M_pad, double nu_lo, double dnu,

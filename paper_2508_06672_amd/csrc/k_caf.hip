@@ -13,7 +13,8 @@
 // interpolation is exact; the Doppler interpolation is the approximation of this form.
 //
 // Kernels
-//   k_caf_extent  FP64 geometry of every (point, step, pair), block min / max of D and nu
+//   k_caf_extent  FP64 geometry of every (point, step, pair), a thread per point; block min / max
+//                 of D and nu
 //                 (sizes and validates the table window on the host)
 //   k_caf_power   sum of |y|^2 per receiver (power-of-two input scale for FP16 range)
 //   k_caf_phasor  F in BF16 or FP16, bin-interleaved: [n / 8][m][8] per plane (re, im), so
@@ -55,19 +56,22 @@ constexpr int kCafKc = GEOLOC_CAF_KC;  // samples staged in LDS per chunk (multi
 
 __global__ __launch_bounds__(256) void k_caf_extent(CafGeomArgs a, double* __restrict__ part) {
     __shared__ double s[4][256];
-    const int64_t total = a.P * a.K * a.n_pairs;
     double dmin = DBL_MAX, dmax = -DBL_MAX, nmin = DBL_MAX, nmax = -DBL_MAX;
-    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
-        const int64_t p = idx % a.P;
-        const int64_t rest = idx / a.P;
-        const int32_t k = (int32_t)(rest % a.K);
-        const int32_t e = (int32_t)(rest / a.K);
-        double D, nu;
-        pair_delay_doppler(a, p, k, e, &D, &nu);
-        dmin = fmin(dmin, D);
-        dmax = fmax(dmax, D);
-        nmin = fmin(nmin, nu);
-        nmax = fmax(nmax, nu);
+    // a thread per point (grid-stride over the points), every pair and step of it in turn:
+    // the point's ECEF is loaded once and the states are the same for the whole block
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < a.P; p += (int64_t)gridDim.x * 256) {
+        const double q0 = a.xyz[3 * p], q1 = a.xyz[3 * p + 1], q2 = a.xyz[3 * p + 2];
+        for (int32_t e = 0; e < a.n_pairs; ++e) {
+            const int2 pr = a.pairs[e];
+            for (int32_t k = 0; k < a.K; ++k) {
+                double D, nu;
+                pair_geometry(q0, q1, q2, a.states, a.n_rx, k, pr, a.fs, a.inv_lambda, &D, &nu);
+                dmin = fmin(dmin, D);
+                dmax = fmax(dmax, D);
+                nmin = fmin(nmin, nu);
+                nmax = fmax(nmax, nu);
+            }
+        }
     }
     const int t = threadIdx.x;
     s[0][t] = dmin;
@@ -367,9 +371,9 @@ __global__ __launch_bounds__(256) void k_caf_interp(CafInterpArgs a) {
 
 // --------------------------------------------------------------------------- launchers
 
-int32_t caf_extent_blocks(int64_t total) {
-    int64_t b = (total + 255) / 256;
-    return (int32_t)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+int32_t caf_extent_blocks(int64_t points) {
+    int64_t b = (points + 255) / 256;
+    return (int32_t)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 hipError_t launch_caf_extent(const CafGeomArgs& a, double* part, int32_t blocks, hipStream_t s) {
