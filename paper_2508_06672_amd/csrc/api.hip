@@ -90,7 +90,6 @@ struct geoloc_plan_s {
     double* d_partial = nullptr;     // [item groups][P]: small grids, or the balanced split of a large one
     int32_t n_groups = 1;            // item groups of a grid too small to fill the GPU
     int32_t max_balance_groups = 1;  // large grids: most item groups a factored launch may be split into
-    int32_t n_cu = 256;              // compute units of the plan's device
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
     bool use_fact = false;           // factored direct kernel (method GEOLOC_DIRECT_FP32)
     bool fact_wide = false;          // its variant with up to 6 Taylor terms (wide Doppler spreads)
@@ -142,7 +141,7 @@ namespace {
 
 bool plan_ok(geoloc_plan_t p) { return p != nullptr && p->magic == kMagic; }
 
-int check_device(int* dev, int* n_cu = nullptr) {
+int check_device(int* dev) {
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || n <= 0) return fail(GEOLOC_EDEVICE, "no HIP device (%s)", hipGetErrorString(e));
@@ -151,7 +150,6 @@ int check_device(int* dev, int* n_cu = nullptr) {
     if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return fail(GEOLOC_EDEVICE, "hipGetDeviceProperties failed");
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(GEOLOC_EDEVICE, "device %d is %s, this library is built for gfx950", *dev, prop.gcnArchName);
-    if (n_cu) *n_cu = prop.multiProcessorCount;
     return GEOLOC_OK;
 }
 
@@ -485,26 +483,17 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     p->fact_wide = q_best > 4;
 }
 
-// Item groups for a factored launch over n_tiles tiles and `items` (pair, step) items when
-// `slots` workgroups fit on the chip at once: the workgroups of a launch run in rounds of
-// `slots`, and a last round that is only partly filled leaves the rest of the chip idle
-// (2160 tiles on 768 slots: three rounds for 2.8 rounds of work). Splitting every tile's
+// Item groups for a factored launch of `items` (pair, step) items over a large grid. The
+// workgroups of a launch run in rounds of as many as fit on the chip at once; a last round
+// that is only partly filled leaves the rest of the chip idle (2160 tiles on 768 slots:
+// three rounds for 2.8 rounds of work), and tiles of unequal work (lag spreads, Taylor
+// orders, cells past the grid edge) leave the same kind of tail. Splitting every tile's
 // items into G groups (G workgroups per tile, each adding its items into a partial row)
-// makes the rounds G times shorter; G minimises rounds x mean items per workgroup, with a small
-// charge per group for the partial rows it writes and the reduction reads.
-int32_t balance_groups(int64_t n_tiles, int64_t items, int64_t slots, int32_t max_groups) {
-    int32_t best = 1;
-    double best_cost = INFINITY;
-    for (int32_t g = 1; g <= max_groups && g <= items; ++g) {
-        const double rounds = (double)((n_tiles * g + slots - 1) / slots);
-        const double per_wg = (double)items / g;
-        const double cost = rounds * per_wg * (1.0 + 0.002 * (g - 1));
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = g;
-        }
-    }
-    return best;
+// makes the workgroups G times shorter, and the tail with them. G is the largest the
+// partial rows allow (on the 1e6-point map: 16.2 ms with one group, 14.4 with six, 13.9
+// with sixteen).
+int32_t balance_groups(int64_t items, int32_t max_groups) {
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(max_groups, items));
 }
 
 int run_geometry(geoloc_plan_t p, int32_t pair_lo, int32_t n_pairs, int64_t k0, int32_t kc, double* D, double* nu,
@@ -842,14 +831,13 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         if (d->step_len > (1ll << 28)) return fail(GEOLOC_EINVAL, "step_len too long for a CAF table");
     }
 
-    int dev = 0, n_cu = 0;
-    int rc = check_device(&dev, &n_cu);
+    int dev = 0;
+    int rc = check_device(&dev);
     if (rc) return rc;
 
     geoloc_plan_t p = new (std::nothrow) geoloc_plan_s();
     if (!p) return fail(GEOLOC_ENOMEM, "host allocation failed");
     p->device = dev;
-    if (n_cu > 0) p->n_cu = n_cu;
     p->n_rx = d->n_rx;
     p->n_pairs = (int32_t)pairs.size();
     p->pairs = pairs;
@@ -1150,9 +1138,7 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         a.defer_flag = p->d_defer_flags + k0 / p->kc;
         a.defer_seq = p->defer_seq;
         if (p->use_fact && a.n_groups == 1 && a.n_segs <= 1 && p->max_balance_groups > 1)
-            a.n_groups = balance_groups(a.n_tiles, (int64_t)kc * p->n_pairs,
-                                        (int64_t)p->n_cu * fact_wgs_per_cu(a, p->delay_mode, p->fact_wide, p->fact_sub),
-                                        p->max_balance_groups);
+            a.n_groups = balance_groups((int64_t)kc * p->n_pairs, p->max_balance_groups);
         if ((rc = span_begin(p, s, &sc, 1))) return rc;
         if (p->use_fact) {
             HIP_TRY(launch_direct_fact(a, p->d_deferred, p->delay_mode, p->fact_wide, p->fact_sub, s));

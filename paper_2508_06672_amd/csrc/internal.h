@@ -142,8 +142,6 @@ __device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
 }
 
 // sub_blocks: 64-sample sub-blocks per Taylor block, 1 or 4
-// Workgroups of the factored kernel resident per CU for this launch's variant.
-int32_t fact_wgs_per_cu(const DirectArgs& a, int32_t delay_mode, bool wide_doppler, int32_t sub_blocks);
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);
@@ -170,15 +168,17 @@ struct GeomArgs {
 };
 
 // Delay and Doppler of one receiver state s = [p; v] against ECEF point q (Sec. II-B,
-// Eq. (3)-(6)): rho = |p - q|, tau = rho / c, f = -(1/lambda) (p - q)/rho . v. Every product
-// and sum is evaluated as written (no FMA contraction).
+// Eq. (3)-(6)): rho = |p - q|, tau = rho / c, f = -(1/lambda) (p - q)/rho . v, with 1/rho
+// taken once (one FP64 division instead of four) and no FMA contraction; the result
+// differs from the expressions written out term by term in the last bits only.
 __device__ inline void delay_doppler(double q0, double q1, double q2, const double* __restrict__ s, double inv_lambda,
                                      double* tau, double* f) {
 #pragma clang fp contract(off)
     const double r0 = s[0] - q0, r1 = s[1] - q1, r2 = s[2] - q2;
     const double rho = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
-    *tau = rho / kLightSpeed;
-    *f = -inv_lambda * ((r0 / rho) * s[3] + (r1 / rho) * s[4] + (r2 / rho) * s[5]);
+    const double inv = 1.0 / rho;
+    *tau = rho * (1.0 / kLightSpeed);
+    *f = -inv_lambda * ((r0 * s[3] + r1 * s[4] + r2 * s[5]) * inv);
 }
 
 // TDOA in samples and FDOA in Hz of the receiver pair pr at ECEF point q and step k

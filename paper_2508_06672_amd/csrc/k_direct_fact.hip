@@ -566,15 +566,6 @@ static void launch_fact_sub(const DirectArgs& a, uint8_t* deferred, int32_t dela
         launch_fact_q<kQMax, kPPT, 1>(a, deferred, delay_mode, s);
 }
 
-int32_t fact_wgs_per_cu(const DirectArgs& a, int32_t delay_mode, bool wide_doppler, int32_t sub_blocks) {
-    // the register budget of the variant launch_fact_q picks (one workgroup per wave per SIMD)
-    if (wide_doppler) return 2;
-    if (sub_blocks != 4) return 3;
-    if (delay_mode != GEOLOC_DELAY_LINEAR) return 4;
-    const int64_t item = a.n_segs > 1 ? (int64_t)a.seg_len : (int64_t)a.L;
-    return item < kLongItem ? 3 : 4;
-}
-
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s) {
     const int lanes = tile_lanes(a.tiling);

@@ -5,9 +5,10 @@
 // Geometry: Sec. II-B, Eq. (3)-(8), delay expressed in samples as in Eq. (9):
 //   r = p_rx - q,  rho = |r|,  tau = rho / c,  f = -(1/lambda) (r / rho) . v_rx,
 //   D = (tau_j - tau_i) f_s,   nu = f_j - f_i.
-// Both kernels evaluate every product and sum as written (no contraction into FMA),
-// which keeps them bit-comparable with a plain FP64 implementation of the same
-// expressions apart from the device's sqrt / sincos rounding.
+// Both kernels evaluate every product and sum as written (no contraction into FMA), which
+// keeps them within a few units in the last place of a plain FP64 implementation of the
+// same expressions (the geometry takes 1/rho once; the device's sqrt and sincos round
+// differently).
 #include "internal.h"
 
 namespace geoloc {
