@@ -330,7 +330,7 @@ def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
     import numpy as np
     import torch
     from paper_2508_06672_amd import proposal as P
-    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=batch)
+    net = P.make_net(geoloc, P.load_weights()[1], max_batch=batch)
     try:
         net.set_params(theta)
         g = torch.Generator(device="cuda").manual_seed(0)
@@ -366,7 +366,7 @@ def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bo
     coarse-map top-16 ablation."""
     from paper_2508_06672_amd import proposal as P
     theta, meta = P.load_weights()
-    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=1)
+    net = P.make_net(geoloc, meta, max_batch=1)
     net.set_params(theta)
     wl = wl or P.TRAIN_WL
     prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"))
@@ -384,6 +384,7 @@ def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bo
             "threshold": meta["threshold"], "n_train": meta.get("n_train"), "params": int(theta.size),
             "full_map_median_ms": res["full_map_median_ms"],
             "median_ms": L["median_ms"], "speedup_vs_full_median": L["speedup_vs_full_median"],
+            "mean_ms": L["mean_ms"], "speedup_vs_full_mean": L["speedup_vs_full_mean"],
             "agree_rate": L["agree_rate"], "fallback_rate": L["fallback_rate"], "rule": L["rule"],
             "ablation_agree_rate": A["agree_rate"], "ablation_rule": A["rule"],
             "ablation_speedup_vs_full_median": A["speedup_vs_full_median"]}
@@ -470,9 +471,10 @@ def c3_leg(geoloc, torch, seeds=(0, 1, 2, 3), reps: int = 5):
 
 def continental_leg(geoloc, torch, seed: int = 0):
     """The continental workload (4000 x 4000 cells at 0.5 km, 3 receivers and 3 pairs, 4e6
-    samples at 20 MHz, two emitters at -20 dB): the plain FP32 map and the BF16 CAF map, each
-    with its top-2 peaks (exclusion radius 8 cells), and whether the CAF peaks fall within one
-    cell of a plain peak or its orbital-plane mirror."""
+    samples at 20 MHz, two emitters at -20 dB): the plain FP32 map, the BF16 CAF map and the
+    combined form (learned proposal with the CAF map as its fallback), each with its top-2
+    peaks (exclusion radius 8 cells), and whether those fall within one cell of a plain peak
+    or its orbital-plane mirror."""
     import numpy as np
     from paper_2508_06672_amd import agreement as A, configs, sim
     wl = configs.CONTINENTAL
@@ -497,11 +499,37 @@ def continental_leg(geoloc, torch, seed: int = 0):
             out[name] = {"map_ms": ms, "value": wl.units / (ms / 1e3), "top2": peaks[name],
                          "top2_vals": [float(v) for v in pv]}
             log(f"  continental {name}: {ms:.1f} ms, top-2 {peaks[name]}")
+    # the combined form: the learned proposal (network trained on the 1024 x 1024 proposal
+    # workload, applied to the 250 x 250 tiles of this grid), falling back to the BF16 CAF map
+    from paper_2508_06672_amd import proposal as P
+    theta, meta = P.load_weights()
+    net = P.make_net(geoloc, meta, max_batch=1, height=wl.n_rows // P.TILE, width=wl.n_cols // P.TILE)
+    net.set_params(theta)
+    prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"),
+                      fallback_method=geoloc.CAF_BF16)
+    try:
+        prop.set_grid(scn.lat, scn.lon)
+        prop.run_top(caps, scn.states, k=2, radius=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = prop.run_top(caps, scn.states, k=2, radius=8)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+    finally:
+        prop.close()
+        net.close()
+    peaks["learned_caf"] = r["idx"]
+    out["learned_caf"] = {"ms": ms, "value": wl.units / (ms / 1e3), "top2": r["idx"], "top2_vals": r["val"],
+                          "fallback": r["fallback"], "score": r["score"]}
+    log(f"  continental learned + CAF fallback: {ms:.1f} ms (fallback {r['fallback']}, score {r['score']:.3f}), "
+        f"top-2 {r['idx']}")
     mirrors = [A.mirror_cell(wl, scn.lat, scn.lon, p) for p in peaks["direct_fp32"]]
     refs = peaks["direct_fp32"] + mirrors
-    out["caf_bf16"]["top2_within_one_cell"] = [min(A.cell_dist(c, r, wl.n_cols) for r in refs) <= 1
-                                               for c in peaks["caf_bf16"]]
+    for name in ("caf_bf16", "learned_caf"):
+        out[name]["top2_within_one_cell"] = [min(A.cell_dist(c, r, wl.n_cols) for r in refs) <= 1
+                                             for c in peaks[name]]
     out["caf_bf16"]["speedup_vs_direct"] = out["direct_fp32"]["map_ms"] / out["caf_bf16"]["map_ms"]
+    out["learned_caf"]["speedup_vs_direct"] = out["direct_fp32"]["map_ms"] / out["learned_caf"]["ms"]
     true = [r * wl.n_cols + c for r, c in scn.true_cells]
     out["direct_fp32"]["true_cells_within_one"] = [min(A.cell_dist(t, p, wl.n_cols) for p in
                                                        peaks["direct_fp32"] + mirrors) <= 1 for t in true]

@@ -926,7 +926,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         const int64_t wgs = base_tiles * p->n_groups;
         if (p->use_fact && wgs < 1024 && p->L >= 8192) {
             // too few (tile, item group) workgroups to fill the GPU, and long steps: also
-            // split every step into coherent segments of whole 2,048-sample LDS tiles
+            // split every step into coherent segments of a multiple of 2,048 samples
             int64_t ns = std::min<int64_t>({(1024 + wgs - 1) / wgs, 16, p->L / 2048});
             if (ns >= 2) {
                 const int64_t len = round_up((p->L + ns - 1) / ns, 2048);

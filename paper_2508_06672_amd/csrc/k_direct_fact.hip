@@ -36,11 +36,13 @@
 namespace geoloc {
 
 constexpr int kFB = 64;          // samples per moment block
-#ifndef GEOLOC_FACT_TB
-#define GEOLOC_FACT_TB 32
-#endif
-constexpr int kFTB = GEOLOC_FACT_TB;   // most blocks per LDS tile
-constexpr int kFT = kFTB * kFB;  // most samples per LDS tile
+// Most 64-sample sub-blocks per LDS tile: 32 (2,048 samples), or 40 for the three-wave
+// variant with 256-sample Taylor blocks, whose LDS (49 KB) still fits three workgroups per
+// CU: ten long blocks per round keep more lanes busy in phase 1 when a tile spans 9 to 12
+// lags (216 or 240 of 256 lanes instead of 192 or 224). The four-wave and wide variants keep
+// 32, which lets four (two) of them share a CU.
+template <int kSub, int kWaves>
+constexpr int fact_tile_sub_blocks() { return (kSub == 4 && kWaves == 3) ? 40 : 32; }
 constexpr int kFQ = 4;           // most Taylor terms of the default variant
 constexpr int kFQWide = 6;       // most Taylor terms of the variant for wide Doppler spreads
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
@@ -323,7 +325,8 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
 template <int kMode, int kQMax, int kPPT, int kSub, int kWaves>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     constexpr int kLB = kSub * kFB;                   // samples per Taylor block
-    __shared__ float2 s_y[kFT + kFH + 4];
+    constexpr int kFTB = fact_tile_sub_blocks<kSub, kWaves>();
+    __shared__ float2 s_y[kFTB * kFB + kFH + 4];
     __shared__ float2 s_v[kFTB * kFVS];
     // [round block][lag][q]: a round holds at most 512 / kSub (block, lag) slots
     __shared__ __align__(16) float2 s_G[kQMax * 512 / kSub];

@@ -20,6 +20,7 @@ FP32 accumulation, trained with Adam by the library's own kernels; PyTorch only 
 the device buffers.
 
 CLI:  python -m paper_2508_06672_amd.proposal train --n-train 4000 --out <weights.npz>
+      python -m paper_2508_06672_amd.proposal calibrate --n-val 1000 --target 0.995
       python -m paper_2508_06672_amd.proposal evaluate --weights <weights.npz> --n-test 200
 """
 from __future__ import annotations
@@ -105,10 +106,10 @@ def band_pairs(pairs, n_rx: int, n_bands: int = BANDS):
     return [(b * n_rx + i, b * n_rx + j) for b in range(n_bands) for (i, j) in pairs]
 
 
-def he_init(seed: int) -> np.ndarray:
+def he_init(seed: int, hidden: int = HIDDEN, layers: int = LAYERS) -> np.ndarray:
     """He-normal convolution weights, zero biases, in the library's flat parameter order."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
-    chans = [IN_CH] + [HIDDEN] * (LAYERS - 1) + [1]
+    chans = [IN_CH] + [hidden] * (layers - 1) + [1]
     out = []
     for ci, co in zip(chans[:-1], chans[1:]):
         out += [rng.standard_normal(co * ci * 9) * math.sqrt(2.0 / (ci * 9)), np.zeros(co)]
@@ -118,6 +119,15 @@ def he_init(seed: int) -> np.ndarray:
 def save_weights(path: str, theta: np.ndarray, meta: dict) -> None:
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.savez(path, theta=np.asarray(theta, dtype=np.float32), meta=np.frombuffer(json.dumps(meta).encode(), np.uint8))
+
+
+def make_net(geoloc, meta: Optional[dict] = None, max_batch: int = 64, height: int = COARSE, width: int = COARSE):
+    """The proposal CNN in the shape the weights' metadata names (the defaults otherwise), on
+    a coarse grid of height x width tiles (the network is fully convolutional, so weights
+    trained on 64 x 64 tiles apply to any coarse grid)."""
+    meta = meta or {}
+    return geoloc.CNN(int(meta.get("in_ch", IN_CH)), int(meta.get("hidden", HIDDEN)), int(meta.get("layers", LAYERS)),
+                      height, width, max_batch=max_batch)
 
 
 def load_weights(path: str = WEIGHTS):
@@ -131,7 +141,10 @@ class Proposer:
     """Plans and network for one fine-grid shape; set_grid() retargets a scenario. Maps take
     the scenario's snapshots stacked as virtual receivers (stack_snapshots)."""
 
-    def __init__(self, wl, net, topk: int = TOPK, threshold: float = 0.5, rule: str = "mass"):
+    def __init__(self, wl, net, topk: int = TOPK, threshold: float = 0.5, rule: str = "mass",
+                 fallback_method: Optional[int] = None):
+        """fallback_method: the method of the full-grid map the proposal falls back to
+        (geoloc.DIRECT_FP32 when None; geoloc.CAF_BF16 gives the combined form)."""
         from . import geoloc
         self.G = geoloc
         self.wl, self.net, self.topk, self.threshold, self.rule = wl, net, topk, threshold, rule
@@ -152,6 +165,9 @@ class Proposer:
         plat, plon, _ = tile_points(lat0, lon0, range(topk))
         self.refine = geoloc.Plan(lat=plat, lon=plon, grid_kind=geoloc.GRID_POINTS, **kw)
         self.full = geoloc.Plan(lat=lat0, lon=lon0, **kw)
+        self.fallback = self.full
+        if fallback_method is not None and fallback_method != geoloc.DIRECT_FP32:
+            self.fallback = geoloc.Plan(lat=lat0, lon=lon0, method=fallback_method, **kw)
         self.lat, self.lon = lat0, lon0
         self._lat_dev = self._lon_dev = None      # the fine grid's axes on the device
         self.n_tile_rows, self.n_tile_cols = wl.n_rows // TILE, wl.n_cols // TILE
@@ -161,9 +177,11 @@ class Proposer:
         self._lat_dev = self._lon_dev = None
         self.coarse.set_grid(*coarse_axes(lat, lon))
         self.full.set_grid(lat, lon)
+        if self.fallback is not self.full:
+            self.fallback.set_grid(lat, lon)
 
     def coarse_features(self, caps, states):
-        """(coarse map [64*64], CNN input [1, 3, 64, 64])."""
+        """(coarse map [tile rows * tile cols], CNN input [1, 3, tile rows, tile cols])."""
         import torch
         if self._bands is None:
             self._bands = torch.empty((BANDS * self.n_vrx, self.wl.n_samples // BANDS), dtype=torch.complex64,
@@ -193,10 +211,49 @@ class Proposer:
         r, c = R * TILE + w // TILE, C * TILE + w % TILE
         return r * self.lon.size + c, float(v[0])
 
+    def refine_peaks(self, caps, states, tiles, k: int, radius: int):
+        """The k largest cells of the given tiles' map, each more than `radius` cells
+        (Chebyshev distance on the fine grid) from the ones before: (flat indices, values)."""
+        if self._lat_dev is None:
+            import torch
+            self._lat_dev = torch.from_numpy(np.ascontiguousarray(self.lat, dtype=np.float64)).to(caps.device)
+            self._lon_dev = torch.from_numpy(np.ascontiguousarray(self.lon, dtype=np.float64)).to(caps.device)
+        tiles = np.asarray(tiles, dtype=np.int64)
+        self.refine.set_points_from_tiles(self._lat_dev, self._lon_dev, TILE, tiles)
+        J = self.refine.map(caps, states).cpu().numpy().astype(np.float64)
+        _, _, flat = tile_points(self.lat, self.lon, tiles)
+        rows, cols = np.divmod(flat, self.lon.size)
+        order = np.argsort(-J, kind="stable")
+        out_i, out_v = [], []
+        for o in order:
+            if all(max(abs(rows[o] - rows[p]), abs(cols[o] - cols[p])) > radius for p in out_i):
+                out_i.append(int(o))
+                out_v.append(float(J[o]))
+                if len(out_i) == k:
+                    break
+        return [int(flat[o]) for o in out_i], out_v
+
     def full_map(self, caps, states):
         J = self.full.map(caps, states)
         i, v = self.full.argmax(J)
         return int(i[0]), float(v[0]), J
+
+    def run_top(self, caps, states, k: int = 2, radius: int = 8) -> Dict:
+        """The learned proposal for k emitters: the CNN's tiles refined at full resolution and
+        the k best separated cells there; below the confidence threshold the fallback plan's
+        full-grid map and its top k (the combined form when that plan is the CAF table)."""
+        Jc, x = self.coarse_features(caps, states)
+        z = self.net.forward(x)
+        tiles, probs = self.net.topk(z, self.topk)
+        tiles, probs = tiles[0], probs[0]
+        score = float(probs[0]) if self.rule == "top1" else float(probs.sum())
+        if score < self.threshold:
+            J = self.fallback.map(caps, states)
+            i, v = self.fallback.argmax(J, top_k=k, nms_radius=radius)
+            return {"idx": [int(t) for t in i], "val": [float(t) for t in v], "fallback": True, "tiles": tiles,
+                    "score": score}
+        i, v = self.refine_peaks(caps, states, tiles, k, radius)
+        return {"idx": i, "val": v, "fallback": False, "tiles": tiles, "score": score}
 
     def run(self, caps, states, selector: str = "cnn") -> Dict:
         """selector: 'cnn' (learned) or 'coarse' (ablation: top tiles of the coarse map itself)."""
@@ -220,6 +277,8 @@ class Proposer:
     def close(self) -> None:
         for p in (self.coarse, self.refine, self.full):
             p.close()
+        if self.fallback is not self.full:
+            self.fallback.close()
 
 
 # --------------------------------------------------------------------------- data
@@ -322,6 +381,23 @@ def calibrate(rec, target: float = 0.99, rule: str = "mass") -> dict:
             "accepted_hit_rate": float(hit[acc].mean()) if acc.any() else None}
 
 
+def calibrate_overall(scores, ok, target: float = 0.99) -> dict:
+    """Smallest threshold on the confidence score for which the whole pipeline (the refined
+    peak where the score reaches the threshold, the full map's own peak where it falls back)
+    agrees with the full map on at least `target` of the scenarios."""
+    sc = np.asarray(scores, dtype=np.float64)
+    ok = np.asarray(ok, dtype=bool)
+    best = float(np.inf)
+    for t in np.unique(sc):
+        if np.mean(ok | (sc < t)) >= target:
+            best = float(t)
+            break
+    acc = sc >= best
+    return {"rule": "mass", "threshold": best, "target": target, "criterion": "overall agreement",
+            "accept_rate": float(acc.mean()), "overall_agreement": float(np.mean(ok | ~acc)),
+            "accepted_agreement": float(ok[acc].mean()) if acc.any() else None}
+
+
 # --------------------------------------------------------------------------- evaluation
 
 AGREE_EPS = 1e-4      # the refine map is the full map's own FP32 values at the chosen cells
@@ -373,8 +449,10 @@ def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
                          "fallback_rate": float(np.mean([r[sel]["fallback"] for r in sub]))}
         return {"agree_rate": float(np.mean(ok)), "fallback_rate": float(np.mean(fb)),
                 "rule": agreement.summarise([r[sel]["rule"] for r in recs], AGREE_EPS),
-                "median_ms": float(np.median(t)), "speedup_vs_full_median": float(np.median(
-                    [r["t_full_ms"] / r[sel]["t_ms"] for r in recs])), "by_waveform": by_wf}
+                "median_ms": float(np.median(t)), "mean_ms": float(np.mean(t)),
+                "speedup_vs_full_median": float(np.median([r["t_full_ms"] / r[sel]["t_ms"] for r in recs])),
+                "speedup_vs_full_mean": float(np.mean([r["t_full_ms"] for r in recs]) / np.mean(t)),
+                "by_waveform": by_wf}
     return {"scenarios": n, "seeds": f"{seeds[0]}..{seeds[-1]}", "workload": wl.name,
             "full_map_median_ms": float(np.median([r["t_full_ms"] for r in recs])),
             "learned": summ("cnn"), "coarse_top16_ablation": summ("coarse"), "records": recs}
@@ -389,9 +467,18 @@ def main(argv=None) -> int:
     t.add_argument("--n-train", type=int, default=6000)
     t.add_argument("--n-val", type=int, default=200)
     t.add_argument("--epochs", type=int, default=20)
+    t.add_argument("--hidden", type=int, default=HIDDEN, help="channels of the hidden layers (at most 32)")
+    t.add_argument("--layers", type=int, default=LAYERS, help="3 x 3 convolutions")
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--workers", type=int, default=16)
     t.add_argument("--out", default=WEIGHTS)
+    c = sub.add_parser("calibrate", help="set the fallback threshold from the full pipeline's agreement on "
+                                          "validation scenarios")
+    c.add_argument("--weights", default=WEIGHTS)
+    c.add_argument("--n-val", type=int, default=1000)
+    c.add_argument("--target", type=float, default=0.995, help="agreement of the whole pipeline on validation")
+    c.add_argument("--workers", type=int, default=16)
+    c.add_argument("--out", default=None, help="where to write the re-calibrated weights (default: in place)")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--n-test", type=int, default=200)
@@ -406,7 +493,8 @@ def main(argv=None) -> int:
     import torch
     from . import geoloc
     assert torch.cuda.is_available()
-    net = geoloc.CNN(IN_CH, HIDDEN, LAYERS, COARSE, COARSE, max_batch=64)
+    meta0 = load_weights(args.weights)[1] if args.cmd != "train" else {"hidden": args.hidden, "layers": args.layers}
+    net = make_net(geoloc, meta0, max_batch=64)
     try:
         if args.cmd == "train":
             wl = TRAIN_WL
@@ -414,12 +502,12 @@ def main(argv=None) -> int:
             log(f"building {args.n_train} training + {args.n_val} validation scenarios ({wl.name})")
             X, Y = build_dataset(prop, wl, list(range(SEED_TRAIN, SEED_TRAIN + args.n_train)), pool)
             Xv, Yv = build_dataset(prop, wl, list(range(SEED_VAL, SEED_VAL + args.n_val)), pool)
-            net.set_params(he_init(0))
+            net.set_params(he_init(0, args.hidden, args.layers))
             hist = train(net, X, Y, Xv, Yv, args.epochs, lr=args.lr)
             _, _, rec = validate(net, Xv, Yv, scores=True)
             cal = calibrate(rec)
             log(f"calibration on the validation set: {cal}")
-            meta = {"in_ch": IN_CH, "hidden": HIDDEN, "layers": LAYERS, "n_params": net.n_params,
+            meta = {"in_ch": IN_CH, "hidden": args.hidden, "layers": args.layers, "n_params": net.n_params,
                     "calibration": cal, "threshold": cal["threshold"], "rule": cal["rule"],
                     "train_workload": wl.name, "n_train": args.n_train, "n_val": args.n_val,
                     "seeds_train": [SEED_TRAIN, SEED_TRAIN + args.n_train], "epochs": args.epochs, "lr": args.lr,
@@ -427,6 +515,28 @@ def main(argv=None) -> int:
             save_weights(args.out, net.params(0), meta)
             log(f"saved {args.out} ({net.n_params} parameters)")
             prop.close()
+        elif args.cmd == "calibrate":
+            # the threshold on the chosen tiles' softmax mass above which the refined peak
+            # agrees with the full map's (agreement rule) at rate >= target on validation
+            # scenarios, every one of them run through the whole pipeline without fallback
+            theta, meta = load_weights(args.weights)
+            net.set_params(theta)
+            wl = TRAIN_WL
+            prop = Proposer(wl, net, threshold=0.0, rule="mass")
+            seeds = list(range(SEED_VAL, SEED_VAL + args.n_val))
+            res = evaluate(prop, wl, seeds, pool)
+            prop.close()
+            cal = calibrate_overall([r["cnn"]["score"] for r in res["records"]],
+                                    [bool(r["cnn"]["ok"]) for r in res["records"]], target=args.target)
+            rec = res["records"]
+            cal.update({"on": "agreement of the refined peak with the full map", "n_val": len(rec),
+                        "seeds": [seeds[0], seeds[-1] + 1]})
+            log(f"calibration on the agreement of {len(rec)} validation scenarios: {cal}")
+            meta["calibration_label_hits"] = meta.get("calibration")
+            meta["calibration"] = cal
+            meta["threshold"] = cal["threshold"]
+            meta["rule"] = "mass"
+            save_weights(args.out or args.weights, theta, meta)
         else:
             theta, meta = load_weights(args.weights)
             net.set_params(theta)

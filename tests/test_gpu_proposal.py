@@ -120,7 +120,7 @@ def test_trained_network_beats_coarse_map_tiles(torch, P):
     16 best tiles of the coarse map itself: what the network adds to the method."""
     from paper_2508_06672_amd import geoloc
     theta, meta = P.load_weights()
-    net = geoloc.CNN(P.IN_CH, P.HIDDEN, P.LAYERS, P.COARSE, P.COARSE, max_batch=64)
+    net = P.make_net(geoloc, meta, max_batch=64)
     net.set_params(theta)
     wl = P.TRAIN_WL
     prop = P.Proposer(wl, net, threshold=0.0)

@@ -82,3 +82,20 @@ def test_agreement_margin_and_classes():
     assert s["n_scenarios"] == 2 and s["well_conditioned_fraction"] == 1.0
     assert s["within_one_cell_well_conditioned"] == 0.5 and s["eps_optimal_all"] == 0.5
     assert A.cell_dist(0, n_cols * 3 + 2, n_cols) == 3
+
+
+def test_proposal_threshold_calibration():
+    """The fallback threshold is the smallest confidence score at which the whole pipeline
+    (refined peak above it, the full map's own peak below it) agrees with the full map on at
+    least the target share of the validation scenarios."""
+    from paper_2508_06672_amd import proposal as P
+    scores = [0.10, 0.50, 0.60, 0.90, 0.95, 0.99]
+    ok = [False, True, False, True, True, True]
+    c = P.calibrate_overall(scores, ok, target=0.8)
+    # at 0.5 the scenario scored 0.6 is accepted and wrong: 5/6 agree; at 0.1 only 4/6
+    assert c["threshold"] == 0.5 and c["overall_agreement"] == pytest.approx(5 / 6)
+    assert c["accept_rate"] == pytest.approx(5 / 6)
+    c = P.calibrate_overall(scores, ok, target=1.0)
+    assert c["threshold"] == 0.9 and c["overall_agreement"] == 1.0 and c["accept_rate"] == 0.5
+    c = P.calibrate_overall([0.3, 0.4], [True, True], target=0.99)
+    assert c["threshold"] == 0.3 and c["accept_rate"] == 1.0
