@@ -153,7 +153,9 @@ typedef struct geoloc_plan_info {
     int64_t device_bytes;      /* device scratch owned by the plan                       */
     int64_t timed_maps;        /* maps run with timing enabled                           */
     int64_t correlate_launches;/* launches of the dominant correlation kernel            */
-    double geometry_ms;        /* summed HIP-event times of the geometry kernels         */
+    double geometry_ms;        /* summed HIP-event times of the geometry kernels (CAF: the
+                                  window fit; the direct method evaluates its geometry
+                                  inside the correlation kernels and reports 0 here)       */
     double correlate_ms;       /* ... of the correlation kernels (direct, or CAF GEMM)   */
     double interp_ms;          /* ... of the CAF interpolation kernels; for the direct
                                   method, of the per-point pass over (tile, step) pairs the
