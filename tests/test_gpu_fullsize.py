@@ -74,7 +74,8 @@ def test_continental_direct_and_caf(torch, G):
     """4000 x 4000 grid at 0.5 km (1.6e7 points), 3 receivers and 3 pairs, 4e6 samples at
     20 MHz in 200 steps, two emitters at -20 dB. The direct map matches the oracle at
     sampled cells and around both of its peaks; the BF16 CAF-table map finds the same two
-    peaks (within one cell, on the orbital-plane mirror, or tol-optimal on the direct map)."""
+    peaks (within one cell, on the orbital-plane mirror, or tol-optimal on the direct map), and so
+    does the combined form (learned proposal, BF16 CAF map as its fallback)."""
     wl = configs.CONTINENTAL
     t0 = time.time()
     scn = sim.make_scenario(wl, 0)
@@ -121,3 +122,22 @@ def test_continental_direct_and_caf(torch, G):
                 return True
         return Jg[a] >= (1 - 1e-2) * Jg[int(pk[1])]
     assert all(agrees(int(a)) for a in ck), (list(ck), list(pk))
+
+    # the combined form: the learned proposal on the grid's 250 x 250 tiles with the BF16 CAF
+    # map as its fallback; whichever way it goes, its two peaks are the direct map's
+    from paper_2508_06672_amd import proposal as P
+    theta, meta = P.load_weights()
+    net = P.make_net(G, meta, max_batch=1, height=wl.n_rows // P.TILE, width=wl.n_cols // P.TILE)
+    net.set_params(theta)
+    prop = P.Proposer(wl, net, threshold=meta["threshold"], rule=meta.get("rule", "mass"),
+                      fallback_method=G.CAF_BF16)
+    try:
+        prop.set_grid(scn.lat, scn.lon)
+        r = prop.run_top(caps, scn.states, k=2, radius=nms)
+    finally:
+        prop.close()
+        net.close()
+    log(f"  combined form: fallback {r['fallback']} (score {r['score']:.3f}), peaks {r['idx']}")
+    if r["fallback"]:
+        assert list(r["idx"]) == [int(a) for a in ck]
+    assert all(agrees(int(a)) for a in r["idx"]), (r["idx"], list(pk))

@@ -50,6 +50,40 @@ def test_zero_weight_network_falls_back_to_the_full_map(torch, P):
     net.close()
 
 
+def test_top_two_peaks_of_refined_tiles(torch, P):
+    """run_top with no fallback: the k best cells of the chosen tiles' map, each more than the
+    exclusion radius from the ones before, read off the full map at those cells (the refine
+    map equals it to FP32 rounding); with a zero-weight network it falls back to the full
+    map's own top-k."""
+    from paper_2508_06672_amd import geoloc
+    wl = SMALL_WL
+    net = geoloc.CNN(3, 32, 4, wl.n_rows // P.TILE, wl.n_cols // P.TILE, max_batch=4)
+    scn, capn, states = _scenario(P, wl, 3)
+    caps = torch.from_numpy(capn).cuda()
+    for threshold, fallback in ((0.0, False), (1.0, True)):
+        prop = P.Proposer(wl, net, threshold=threshold)
+        prop.set_grid(scn.lat, scn.lon)
+        r = prop.run_top(caps, states, k=2, radius=3)
+        _, _, Jf = prop.full_map(caps, states)
+        Jf = Jf.cpu().numpy().astype(np.float64)
+        assert r["fallback"] == fallback and len(r["idx"]) == 2
+        if fallback:
+            i, v = prop.full.argmax(prop.full.map(caps, states), top_k=2, nms_radius=3)
+            assert list(r["idx"]) == [int(t) for t in i]
+        else:
+            # the same cells on the full map: the refined tiles' best two, 3 cells apart
+            _, _, flat = P.tile_points(scn.lat, scn.lon, r["tiles"])
+            Js = Jf[flat]
+            a, b = r["idx"]
+            assert Jf[a] >= (1 - 2e-5) * Js.max()
+            ra, ca = divmod(a, wl.n_cols)
+            far = [f for f in flat if max(abs(f // wl.n_cols - ra), abs(f % wl.n_cols - ca)) > 3]
+            assert max(abs(b // wl.n_cols - ra), abs(b % wl.n_cols - ca)) > 3
+            assert Jf[b] >= (1 - 2e-5) * Jf[far].max()
+        prop.close()
+    net.close()
+
+
 def test_refined_tiles_reproduce_the_full_map(torch, P):
     """The refine map (a POINTS grid of whole tiles) at the chosen tiles' cells equals the
     full-grid map at those cells to FP32 rounding (the full grid may use sheared tiles, so
