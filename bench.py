@@ -358,14 +358,14 @@ def train_step_leg(geoloc, theta, batch: int = 64, reps: int = 20):
     return {"batch": batch, "ms": ms, "samples_per_s": batch / (ms / 1e3), "params": int(theta.size)}
 
 
-def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bool = True):
+def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bool = True, weights=None):
     """The learned tile proposal with its stored weights and calibrated fallback on held-out
     proposal scenarios (the training workload unless wl is given): median time against the
     full plain map of the same scenario, and how often its argmax agrees with the full
     map's (within one cell, on the orbital-plane mirror, or tol-optimal), beside the
     coarse-map top-16 ablation."""
     from paper_2508_06672_amd import proposal as P
-    theta, meta = P.load_weights()
+    theta, meta = P.load_weights(weights or P.WEIGHTS)
     net = P.make_net(geoloc, meta, max_batch=1)
     net.set_params(theta)
     wl = wl or P.TRAIN_WL
@@ -380,7 +380,9 @@ def learned_leg(geoloc, seeds, pool=None, out_path=None, wl=None, train_step: bo
             json.dump(res, fh)
     L, A = res["learned"], res["coarse_top16_ablation"]
     train = train_step_leg(geoloc, theta) if train_step else None
-    return {"workload": wl.name, "scenarios": res["scenarios"], "seeds": res["seeds"], "train_step": train,
+    return {"workload": wl.name, "weights": os.path.basename(weights or P.WEIGHTS),
+            "train_workload": meta.get("train_workload"), "scenarios": res["scenarios"], "seeds": res["seeds"],
+            "train_step": train,
             "threshold": meta["threshold"], "n_train": meta.get("n_train"), "params": int(theta.size),
             "full_map_median_ms": res["full_map_median_ms"],
             "median_ms": L["median_ms"], "speedup_vs_full_median": L["speedup_vs_full_median"],
@@ -593,7 +595,8 @@ def main() -> int:
                     help="held-out scenarios (seeds 1030000..) for the learned-proposal leg (0 skips it)")
     ap.add_argument("--c4-seeds", type=int, default=200,
                     help="held-out scenarios (seeds 1030000..) of the single-capture 100 ms workload on which the "
-                         "learned proposal (trained on the 10-capture workload) is also evaluated (0 skips it)")
+                         "learned proposal is also evaluated, with the network trained on that workload when its "
+                         "weights are present (0 skips it)")
     ap.add_argument("--study", action="store_true",
                     help="the full agreement study: 1000 CAF seeds and 300 learned-proposal seeds, with "
                          "per-scenario records written under --study-out")
@@ -730,7 +733,9 @@ def main() -> int:
         log(f"learned proposal on the single-capture workload over {args.c4_seeds} held-out scenarios")
         learned_c4 = learned_leg(geoloc, list(range(P.SEED_TEST, P.SEED_TEST + args.c4_seeds)), pool,
                                  out_path=os.path.join(rec_dir, "agreement_learned_c4.json") if rec_dir else None,
-                                 wl=configs.PROPOSAL_C4, train_step=False)
+                                 wl=configs.PROPOSAL_C4, train_step=False,
+                                 weights=P.WEIGHTS_SINGLE_CAPTURE if os.path.exists(P.WEIGHTS_SINGLE_CAPTURE)
+                                 else None)
 
     paper = None
     if not args.no_paper_scenario:

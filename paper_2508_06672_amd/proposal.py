@@ -45,6 +45,8 @@ BANDS, BAND_HALF_TAPS = 16, 64          # coarse-map sub-bands: 16 bands, 129-ta
 LABEL_EPS = 1e-2
 IN_CH, HIDDEN, LAYERS = 3, 32, 4
 TRAIN_WL = configs.PROPOSAL
+WORKLOADS = {"proposal": configs.PROPOSAL, "single_capture": configs.PROPOSAL_C4}
+WEIGHTS_SINGLE_CAPTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal_cnn_c4.npz")
 SEED_TRAIN, SEED_VAL, SEED_TEST = 1_000_000, 1_020_000, 1_030_000
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "proposal_cnn.npz")
 
@@ -460,6 +462,16 @@ def evaluate(prop: Proposer, wl, seeds, pool) -> dict:
 
 # --------------------------------------------------------------------------- CLI
 
+def _workload_of(name, meta):
+    """The named workload, else the one the weights were trained on."""
+    if name:
+        return WORKLOADS[name]
+    for w in WORKLOADS.values():
+        if w.name == meta.get("train_workload"):
+            return w
+    return TRAIN_WL
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -469,6 +481,7 @@ def main(argv=None) -> int:
     t.add_argument("--epochs", type=int, default=20)
     t.add_argument("--hidden", type=int, default=HIDDEN, help="channels of the hidden layers (at most 32)")
     t.add_argument("--layers", type=int, default=LAYERS, help="3 x 3 convolutions")
+    t.add_argument("--workload", choices=sorted(WORKLOADS), default="proposal")
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--workers", type=int, default=16)
     t.add_argument("--out", default=WEIGHTS)
@@ -479,13 +492,17 @@ def main(argv=None) -> int:
     c.add_argument("--target", type=float, default=0.995, help="agreement of the whole pipeline on validation")
     c.add_argument("--workers", type=int, default=16)
     c.add_argument("--out", default=None, help="where to write the re-calibrated weights (default: in place)")
+    c.add_argument("--workload", choices=sorted(WORKLOADS), default=None,
+                   help="default: the workload the weights were trained on")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--n-test", type=int, default=200)
-    e.add_argument("--samples", type=int, default=configs.PROPOSAL.n_samples)
+    e.add_argument("--samples", type=int, default=0, help="capture length (default: the workload's)")
     e.add_argument("--workers", type=int, default=16)
     e.add_argument("--out", default=None)
     e.add_argument("--threshold", type=float, default=None, help="override the calibrated threshold")
+    e.add_argument("--workload", choices=sorted(WORKLOADS), default=None,
+                   help="default: the workload the weights were trained on")
     args = ap.parse_args(argv)
 
     # simulator workers are forked before anything touches the GPU
@@ -497,7 +514,7 @@ def main(argv=None) -> int:
     net = make_net(geoloc, meta0, max_batch=64)
     try:
         if args.cmd == "train":
-            wl = TRAIN_WL
+            wl = WORKLOADS[args.workload]
             prop = Proposer(wl, net)
             log(f"building {args.n_train} training + {args.n_val} validation scenarios ({wl.name})")
             X, Y = build_dataset(prop, wl, list(range(SEED_TRAIN, SEED_TRAIN + args.n_train)), pool)
@@ -521,7 +538,7 @@ def main(argv=None) -> int:
             # scenarios, every one of them run through the whole pipeline without fallback
             theta, meta = load_weights(args.weights)
             net.set_params(theta)
-            wl = TRAIN_WL
+            wl = _workload_of(args.workload, meta)
             prop = Proposer(wl, net, threshold=0.0, rule="mass")
             seeds = list(range(SEED_VAL, SEED_VAL + args.n_val))
             res = evaluate(prop, wl, seeds, pool)
@@ -540,7 +557,9 @@ def main(argv=None) -> int:
         else:
             theta, meta = load_weights(args.weights)
             net.set_params(theta)
-            wl = configs.PROPOSAL.with_(n_samples=args.samples)
+            wl = _workload_of(args.workload, meta)
+            if args.samples:
+                wl = wl.with_(n_samples=args.samples)
             thr = args.threshold if args.threshold is not None else meta.get("threshold", 0.5)
             prop = Proposer(wl, net, threshold=thr, rule=meta.get("rule", "mass"))
             log(f"threshold {thr} ({meta.get('rule', 'mass')})")
