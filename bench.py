@@ -696,6 +696,11 @@ def main() -> int:
                 "tile": f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f} columns/row"
                         f"{' transposed' if info['tile_transpose'] else ''}",
                 "taylor_block": info["taylor_block"],
+                # the build leaves out the packed FP32 forms that the 157.3 figure counts
+                "frac_of_unpacked_fp32": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
+                # captures, grid ECEF and J once per launch
+                "algorithmic_bytes": (wl.n_rx * wl.n_samples * 8 + wl.n_points * (24 + 4)) * info["timed_maps"]
+                                     / launches,
                 "pointwise_equivalent_tflops": round(FLOP_PER_UNIT_POINTWISE * units_per_launch / (k_ms / 1e3) / 1e12,
                                                      3)}
 
