@@ -99,3 +99,24 @@ def test_proposal_threshold_calibration():
     assert c["threshold"] == 0.9 and c["overall_agreement"] == 1.0 and c["accept_rate"] == 0.5
     c = P.calibrate_overall([0.3, 0.4], [True, True], target=0.99)
     assert c["threshold"] == 0.3 and c["accept_rate"] == 1.0
+
+
+def test_bandlimited_noise_interpolator():
+    """The tabulated-window interpolator of the synthetic noise reproduces its samples at the
+    sample instants (also just below them, where sin(pi fr) cancels) and agrees with the
+    Kaiser-windowed sinc written out directly."""
+    rng = np.random.default_rng(3)
+    g = sim.BandlimitedGaussian(rng, 10e6, 0, 4000)
+    k = np.arange(100, 3900)
+    t = k / g.fs
+    assert np.abs(g(t) - g.g[k - g.m_lo]).max() < 1e-11
+    t = rng.uniform(100, 3900, 20000) / g.fs
+    u = t * g.fs
+    base = np.floor(u).astype(np.int64)
+    fr = u - base
+    ref = np.zeros(u.shape, dtype=np.complex128)
+    for q in range(-g.HALF + 1, g.HALF + 1):
+        z = fr - q
+        w = np.i0(g.BETA * np.sqrt(np.clip(1.0 - (z / g.HALF) ** 2, 0.0, None))) / np.i0(g.BETA)
+        ref += g.g[base + q - g.m_lo] * np.sinc(z) * w
+    assert np.abs(g(t) - ref).max() < 1e-8
