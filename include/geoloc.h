@@ -59,7 +59,7 @@ extern "C" {
 /* method */
 #define GEOLOC_DIRECT_FP32   0   /* Eq. (11) in FP32 with FP64 geometry; the per-point sums
                                     are factored through lag moments shared by a tile of
-                                    points (256 or 512 cells of a RECT grid in a slanted tile
+                                    points (256, 512 or 1024 cells of a RECT grid in a slanted tile
                                     chosen per map, 256 consecutive points of a POINTS
                                     list), with a Taylor remainder of at
                                     most 2^-24 of each Taylor block's magnitude sum (blocks
@@ -161,7 +161,7 @@ typedef struct geoloc_plan_info {
                                   method, of the per-point pass over (tile, step) pairs the
                                   factored kernel left to it                              */
     double map_ms;             /* ... of whole geoloc_map calls, first to last kernel    */
-    int32_t tile_rows, tile_cols;   /* tile of the last map: rows x cells per row (256 or 512 cells) */
+    int32_t tile_rows, tile_cols;   /* tile of the last map: rows x cells per row (256, 512 or 1024 cells) */
     int32_t tile_shear;        /* column shift per tile row, in 1/256 columns (slanted tiles) */
     int32_t tile_transpose;    /* 1: rows and columns swap roles in the tile              */
     int32_t step_segments;     /* direct method: coherent segments each step is split into
@@ -203,7 +203,8 @@ int geoloc_set_points_from_tiles(geoloc_plan_t plan, const double* lat_dev, cons
 
 /* Fix the tiling of the tile-factored kernel for the maps that follow (RECT grids, method
  * GEOLOC_DIRECT_FP32), instead of the per-map choice from the geometry: tiles of tile_h rows
- * of tile_w cells (tile_w x tile_h = 256, or 512 for two cells per thread; SINC 256 only),
+ * of tile_w cells (tile_w x tile_h = 256, or 512 or 1024 for two or four cells per thread;
+ * SINC 256 only),
  * row i starting floor(shear * i / 256) columns further along, |shear| <= 1024, rows and
  * columns swapped if transpose. tile_w = 0 returns to the per-map choice. The map is the
  * same function of the inputs whatever the tiling (to FP32 rounding); only its speed and

@@ -81,13 +81,15 @@ struct geoloc_plan_s {
     int32_t kc = 1;  // steps per correlation launch
     // device scratch
     double* d_xyz = nullptr;
+    double2* d_ecef_row = nullptr;   // RECT grid with a uniform height: ECEF row and column factors
+    double2* d_ecef_col = nullptr;
     double* d_lat = nullptr;         // grid coordinates as given (kept for geoloc_set_grid)
     double* d_lon = nullptr;
     double* d_states = nullptr;
     int2* d_pairs = nullptr;
     uint32_t* d_defer_flags = nullptr;   // [step chunks] deferral flag of each correlation launch
     uint32_t defer_seq = 0;              // sequence number of the current map (never 0)
-    double* d_partial = nullptr;     // [item groups][P]: small grids, or the balanced split of a large one
+    float* d_partial = nullptr;      // [item groups][P]: small grids, or the balanced split of a large one
     int32_t n_groups = 1;            // item groups of a grid too small to fill the GPU
     int32_t max_balance_groups = 1;  // large grids: most item groups a factored launch may be split into
     uint8_t* d_deferred = nullptr;   // [n_pairs][kc][n_tiles] steps left to the per-point kernel
@@ -169,6 +171,8 @@ int dev_alloc(geoloc_plan_t p, T** out, size_t count) {
 void release(geoloc_plan_t p) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_xyz);
+    (void)hipFree(p->d_ecef_row);
+    (void)hipFree(p->d_ecef_col);
     (void)hipFree(p->d_alt);
     (void)hipFree(p->d_tiles);
     (void)hipFree(p->d_lat);
@@ -298,7 +302,7 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 }
 
 // Tile shape for the factored kernel: from the delay and Doppler gradients at the grid
-// centre (middle step) of every pair, the candidate (shape of 256 or 512 cells, shear of
+// centre (middle step) of every pair, the candidate (shape of 256, 512 or 1024 cells, shear of
 // whole columns per row or along a pair's lines of equal delay) with the least predicted
 // VALU work per correlation summed over the pairs, counting the lanes its tiles leave
 // outside the grid. The lag moments cost about (8 + 4Q) instructions per lag pair and
@@ -311,9 +315,15 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // fewer than 768 workgroups (three per CU) is charged for the idle share of the chip, and
 // SINC keeps to 256-cell tiles at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
-// are counted 1.5 times, and the variant is launched when the chosen tiling needs them. A
-// fixed tiling (geoloc_set_tiling) keeps its shape and never takes the wide variant; only
-// its block length is chosen.
+// are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
+// Tiles of 1024 cells (four per thread, LINEAR and ROUND, at most four Taylor terms) share
+// each moment among twice as many cells, at three waves per SIMD like the 256- and 512-cell
+// LINEAR kernels; where those run four (ROUND, and LINEAR items of at least kLongItem
+// samples, with 256-sample blocks) the 1024-cell work is counted 1.15 times. On the 1e6-point
+// map the LINEAR map took 10.3 ms on 16 x 64 tiles against 13.7 ms on 8 x 64 (the model's
+// ratio 0.81), ROUND 9.6 ms on 8 x 128 against 11.0 ms (model 0.76). A
+// fixed tiling (geoloc_set_tiling) keeps its shape and never takes the wide variant; only its
+// block length is chosen.
 void choose_tiling(geoloc_plan_t p, const double* states) {
     p->tiling = p->tiling_fixed ? p->fixed_tiling : p->base_tiling;
     p->fact_wide = false;
@@ -386,13 +396,13 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         return std::max(valu, 4.0 * reads * Q);
     };
     const double taps = p->delay_mode == GEOLOC_DELAY_SINC ? 8.0 : 2.0;   // lags each cell reads
-    const int q_allowed = p->tiling_fixed ? 4 : 6;
     auto cost = [&](const PointTiling& t, int sub, int* q_need) {
         double total = 0.0;
         *q_need = 0;
         const double sh = (double)t.shear / kShearOne;
         const double jag = (t.shear % kShearOne) ? 1.0 : 0.0;   // rounding of fractional row offsets
         const int lanes = tile_lanes(t);
+        const int q_allowed = (p->tiling_fixed || lanes == 1024) ? 4 : 6;
         const double Rn = (double)(t.transpose ? p->cols : p->rows), Cn = (double)(t.transpose ? p->rows : p->cols);
         const double hl = t.tile_h - 1.0, wl = t.tile_w - 1.0 + jag;
         // spread over a tile of a quantity with gradient (fr, fc) and second derivatives
@@ -432,7 +442,13 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
             }
             total += weight[gi] * c;
         }
-        return total * (double)(t.tiles_x * t.tiles_y * lanes) / (double)p->P * fill(t);
+        double occupancy = 1.0;
+        if (lanes == 1024) {
+            const int64_t item = p->n_segs > 1 ? p->seg_len : p->L;
+            const bool four = sub == 4 && (p->delay_mode == GEOLOC_DELAY_ROUND || item >= kLongItem);
+            occupancy = four ? 1.15 : 1.0;
+        }
+        return total * (double)(t.tiles_x * t.tiles_y * lanes) / (double)p->P * fill(t) * occupancy;
     };
     int q_best = 0, q = 0;
     std::vector<int> subs = {1, 4};
@@ -880,9 +896,10 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
         p->base_tiling = p->tiling = t;
         p->max_tiles = t.tiles_x * t.tiles_y;
         if (d->grid_kind == GEOLOC_GRID_RECT) {
-            // tile shapes of 256 and 512 cells, either way round; the map picks one and its
-            // shear from the geometry, with |shear| <= kMaxShear (scratch is sized for that)
-            const int shapes[6][2] = {{16, 16}, {8, 32}, {4, 64}, {16, 32}, {8, 64}, {4, 128}};
+            // tile shapes of 256, 512 and 1024 cells, either way round; the map picks one and
+            // its shear from the geometry, with |shear| <= kMaxShear (scratch is sized for that)
+            const int shapes[10][2] = {{16, 16}, {8, 32}, {4, 64}, {16, 32}, {8, 64},
+                                       {4, 128}, {32, 32}, {16, 64}, {8, 128}, {4, 256}};
             for (int tr = 0; tr < 2; ++tr)
                 for (const auto& wh : shapes) {
                     PointTiling c = t;
@@ -912,6 +929,10 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
 
     do {
         if ((rc = dev_alloc(p, &p->d_xyz, (size_t)P * 3))) break;
+        if (d->grid_kind == GEOLOC_GRID_RECT && !d->alt_grid &&
+            ((rc = dev_alloc(p, &p->d_ecef_row, (size_t)d->n_rows)) ||
+             (rc = dev_alloc(p, &p->d_ecef_col, (size_t)d->n_cols))))
+            break;
         if ((rc = dev_alloc(p, &p->d_states, (size_t)p->K * p->n_rx * 6))) break;
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
         if ((rc = dev_alloc(p, &p->d_defer_flags, (size_t)n_chunks))) break;
@@ -941,7 +962,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
             // a large grid: its factored launches may be split into item groups so that the
             // workgroup count fills whole rounds of the chip (partial rows within a budget)
             p->max_balance_groups = (int32_t)std::max<int64_t>(
-                1, std::min<int64_t>({kMaxBalanceGroups, items, kBalanceBytes / (8 * P)}));
+                1, std::min<int64_t>({kMaxBalanceGroups, items, kBalanceBytes / ((int64_t)sizeof(float) * P)}));
             if (p->max_balance_groups > 1 &&
                 (rc = dev_alloc(p, &p->d_partial, (size_t)p->max_balance_groups * P)))
                 break;
@@ -975,7 +996,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
             e = hipMemcpy(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_grid_ecef(p->d_lat, p->d_lon, d->grid_kind, d->n_rows, d->n_cols, p->earth_model, p->radius,
-                                 p->alt, p->d_alt, p->d_xyz, nullptr);
+                                 p->alt, p->d_alt, p->d_ecef_row, p->d_ecef_col, p->d_xyz, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             rc = fail(GEOLOC_ELAUNCH, "plan set-up: %s", hipGetErrorString(e));
@@ -1006,7 +1027,7 @@ int geoloc_set_grid(geoloc_plan_t p, const double* lat, const double* lon) {
     HIP_TRY(hipMemcpy(p->d_lat, lat, n_lat * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_lon, lon, n_lon * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->earth_model, p->radius, p->alt,
-                             nullptr, p->d_xyz, nullptr));
+                             nullptr, p->d_ecef_row, p->d_ecef_col, p->d_xyz, nullptr));
     HIP_TRY(hipDeviceSynchronize());
     return GEOLOC_OK;
 }
@@ -1033,7 +1054,7 @@ int geoloc_set_points_from_tiles(geoloc_plan_t p, const double* lat_dev, const d
     HIP_TRY(hipMemcpyAsync(p->d_tiles, tiles, (size_t)n_tiles * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_tile_points(lat_dev, lon_dev, rows, cols, tile, p->d_tiles, p->P, p->d_lat, p->d_lon, s));
     HIP_TRY(launch_grid_ecef(p->d_lat, p->d_lon, p->grid_kind, p->rows, p->cols, p->earth_model, p->radius, p->alt,
-                             nullptr, p->d_xyz, s));
+                             nullptr, nullptr, nullptr, p->d_xyz, s));
     // the host copy of the grid serves the tile choice of RECT plans only
     p->h_lat.clear();
     p->h_lon.clear();
@@ -1049,8 +1070,8 @@ int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t s
     if (p->grid_kind != GEOLOC_GRID_RECT || p->method != GEOLOC_DIRECT_FP32)
         return fail(GEOLOC_EINVAL, "a fixed tiling needs a RECT grid and GEOLOC_DIRECT_FP32");
     const int64_t cells = (int64_t)tile_w * tile_h;
-    if (tile_w < 1 || tile_h < 1 || (cells != 256 && cells != 512))
-        return fail(GEOLOC_EINVAL, "tile must hold 256 or 512 cells (got %d x %d)", tile_w, tile_h);
+    if (tile_w < 1 || tile_h < 1 || (cells != 256 && cells != 512 && cells != 1024))
+        return fail(GEOLOC_EINVAL, "tile must hold 256, 512 or 1024 cells (got %d x %d)", tile_w, tile_h);
     if (cells != kTilePoints && p->delay_mode == GEOLOC_DELAY_SINC)
         return fail(GEOLOC_EINVAL, "SINC takes 256-cell tiles");
     if (shear < -kMaxShear || shear > kMaxShear) return fail(GEOLOC_EINVAL, "|shear| must be <= %d", kMaxShear);
@@ -1112,6 +1133,8 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         DirectArgs a{};
         a.cap = (const float2*)in->captures;
         a.xyz = p->d_xyz;
+        a.ecef_row = p->d_ecef_row;
+        a.ecef_col = p->d_ecef_col;
         a.states = p->d_states;
         a.n_rx = p->n_rx;
         a.fs = p->fs;

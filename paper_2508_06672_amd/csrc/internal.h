@@ -16,7 +16,7 @@ constexpr double kWgs84A = 6378137.0;             // WGS-84 semi-major axis (m)
 constexpr double kWgs84F = 1.0 / 298.257223563;   // WGS-84 flattening
 
 // Points handled by one workgroup of the correlation kernels: a tile of 256 (or, for the
-// factored kernel, 512) cells of a RECT grid (neighbouring cells have neighbouring delays,
+// factored kernel, 512 or 1024) cells of a RECT grid (neighbouring cells have neighbouring delays,
 // so the lag spread a tile needs in LDS stays small), or 256 consecutive entries of a
 // POINTS list.
 //
@@ -26,7 +26,6 @@ constexpr double kWgs84F = 1.0 / 298.257223563;   // WGS-84 flattening
 // rows; each band holds tiles_x tiles, enough to cover the sheared band, and cells outside
 // the grid are invalid lanes. shear = 0, 16 x 16 is the plain square tiling.
 constexpr int kTilePoints = 256;       // cells of the square tiling and of POINTS tiles
-constexpr int kMaxTileLanes = 512;     // most cells of any tile
 constexpr int kShearOne = 256;         // shear unit: one column per row
 
 struct PointTiling {
@@ -69,6 +68,11 @@ struct DirectArgs {
     const float2* cap;       // [n_rx][N] complex64
     // geometry, evaluated inline per (point, step, pair) in FP64 (Eq. (3)-(9))
     const double* xyz;       // [P][3] ECEF of the grid points
+    // rectilinear grid with a uniform height (else NULL): the ECEF of point p = r cols + c is
+    // (ecef_row[r].x ecef_col[c].x, ecef_row[r].x ecef_col[c].y, ecef_row[r].y), the same
+    // products xyz holds
+    const double2* ecef_row;
+    const double2* ecef_col;
     const double* states;    // [K][n_rx][6] receiver position and velocity per step
     int32_t n_rx;
     double fs, inv_lambda;
@@ -82,7 +86,7 @@ struct DirectArgs {
     int32_t accum_mode;
     int32_t load_J;          // add onto the existing J values
     int32_t n_groups;        // groups of (pair, step) items per chunk (1: each workgroup owns its points' J)
-    double* partial;         // [n_groups][P] partial sums when n_groups > 1
+    float* partial;          // [n_groups][P] partial sums when n_groups > 1
     const uint8_t* mask;     // [n_pairs][kc][n_tiles]: nonzero = this kernel handles it; NULL = all
     // deferral flag of this launch: the factored kernel stores defer_seq into *defer_flag
     // when it leaves any (tile, step) to the per-point kernel, whose masked pass returns at
@@ -154,6 +158,11 @@ hipError_t launch_gather_noise(const float* noise, const int64_t* idx, int32_t k
 hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s);
 
 constexpr int32_t kMaxItemGroups = 64;
+// Items of at least this many samples (a step, or a segment of one) take the four-wave
+// budget in the factored kernel's LINEAR mode with 256-sample blocks; shorter ones pay its
+// spills too often (on the 1e6-point map, steps of 10,000 samples, it ran 2 % slower, while
+// 250,000-sample steps ran 23 % faster).
+constexpr int64_t kLongItem = 32768;
 int32_t direct_groups(int64_t n_tiles, int64_t n_items);   // n_items = pairs x steps per chunk
 
 struct GeomArgs {
@@ -244,8 +253,8 @@ struct CafInterpArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
-                            int32_t model, double radius, double alt, const double* alt_p, double* xyz,
-                            hipStream_t s);
+                            int32_t model, double radius, double alt, const double* alt_p, double2* row_tab,
+                            double2* col_tab, double* xyz, hipStream_t s);
 hipError_t launch_geometry(const GeomArgs& a, hipStream_t s);
 hipError_t launch_tile_points(const double* glat, const double* glon, int64_t rows, int64_t cols, int32_t tile,
                               const int32_t* tiles, int64_t P, double* lat, double* lon, hipStream_t s);

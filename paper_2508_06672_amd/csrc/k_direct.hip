@@ -147,7 +147,7 @@ void k_direct(DirectArgs a) {
     // item groups: a masked pass adds onto the partial sums the factored kernel wrote
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
-    if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
+    if (valid && a.n_groups > 1 && a.mask) jacc = (double)a.partial[(int64_t)group * a.P + p];
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
@@ -229,16 +229,16 @@ void k_direct(DirectArgs a) {
     if (a.n_groups == 1)
         a.J[p] = (float)jacc;
     else
-        a.partial[(int64_t)group * a.P + p] = jacc;
+        a.partial[(int64_t)group * a.P + p] = (float)jacc;
 }
 
 // J[p] = (J[p] if loading) + sum over item groups of the partial sums, in group order.
-__global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict__ partial, int32_t n_groups, int64_t P,
+__global__ __launch_bounds__(256) void k_direct_reduce(const float* __restrict__ partial, int32_t n_groups, int64_t P,
                                                        int32_t load_J, float* __restrict__ J) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
     double acc = load_J ? (double)J[p] : 0.0;
-    for (int g = 0; g < n_groups; ++g) acc += partial[(int64_t)g * P + p];
+    for (int g = 0; g < n_groups; ++g) acc += (double)partial[(int64_t)g * P + p];
     J[p] = (float)acc;
 }
 
@@ -262,7 +262,7 @@ hipError_t launch_direct(const DirectArgs& a, int32_t delay_mode, hipStream_t s)
 hipError_t launch_direct_reduce(const DirectArgs& a, hipStream_t s) {
     if (a.n_groups == 1) return hipSuccess;
     hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s,
-                       (const double*)a.partial, a.n_groups, a.P, a.load_J, a.J);
+                       (const float*)a.partial, a.n_groups, a.P, a.load_J, a.J);
     return hipGetLastError();
 }
 

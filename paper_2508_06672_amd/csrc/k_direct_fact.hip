@@ -1,7 +1,7 @@
 // k_direct_fact.hip -- direct position-domain correlation (Sec. III, Eq. (11)) with the
 // per-point work factored through lag moments shared by a tile of points.
 //
-// Within a tile of 256 or 512 candidate points (a slanted parallelogram that follows the
+// Within a tile of 256, 512 or 1024 candidate points (a slanted parallelogram that follows the
 // lines of equal delay) the delays and Doppler shifts of one step are close. Split the step
 // into blocks of B = 64 samples (block centre c_b, sample offset r = n - c_b in [-31.5,
 // 31.5]) and write each point's rotation rate as the tile's mean plus a small deviation,
@@ -317,11 +317,12 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
 }
 
 // kMode: GEOLOC_DELAY_LINEAR, _ROUND or _SINC; kQMax: most Taylor terms; kPPT: points per
-// thread (tiles of 256 kPPT cells); kSub: 64-sample sub-blocks per Taylor block (1 or 4);
-// kWaves: waves per SIMD the register budget is set for (which the compiler does not always
-// choose by itself). Three workgroups per CU, two for the wide variant (its LDS allows no
-// more); with 256-sample blocks the LDS allows four, at 128 VGPRs, whose spills fall in the
-// per-item set-up: the launcher takes that budget where items are long.
+// thread (tiles of 256 kPPT cells: 1, 2, or 4 for LINEAR and ROUND); kSub: 64-sample
+// sub-blocks per Taylor block (1 or 4); kWaves: waves per SIMD the register budget is set
+// for (which the compiler does not always choose by itself). Three workgroups per CU, two
+// for the wide variant (its LDS allows no more); with 256-sample blocks the LDS allows four,
+// at 128 VGPRs, whose spills fall in the per-item set-up: the launcher takes that budget
+// where items are long, except with four points per thread.
 template <int kMode, int kQMax, int kPPT, int kSub, int kWaves>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_direct_fact(DirectArgs a, uint8_t* __restrict__ deferred) {
     constexpr int kLB = kSub * kFB;                   // samples per Taylor block
@@ -360,15 +361,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
             if (valid[k]) a.cpart[((int64_t)seg * a.n_pairs * a.kc + it) * a.P + p[k]] = make_float2(0.f, 0.f);
     };
 
-    // ECEF of this thread's points (an invalid lane takes point 0's, whose values it never
-    // uses), for the FP64 geometry of every item
-    double qx[kPPT], qy[kPPT], qz[kPPT];
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-        qx[k] = a.xyz[3 * p[k]];
-        qy[k] = a.xyz[3 * p[k] + 1];
-        qz[k] = a.xyz[3 * p[k] + 2];
-    }
+    // ECEF of point k of this thread (an invalid lane takes point 0's, whose values it never
+    // uses), for the FP64 geometry of every item: read again per item (from L2) rather than
+    // held in registers through the phase loops; a rectilinear grid forms it from its row and
+    // column factors, which a tile's workgroups share
+    auto point_ecef = [&](int k, double& x, double& y, double& z) {
+        if (a.ecef_row) {
+            const int64_t r = p[k] / a.tiling.cols;
+            const double2 A = a.ecef_row[r], C = a.ecef_col[p[k] - r * a.tiling.cols];
+            x = A.x * C.x;
+            y = A.x * C.y;
+            z = A.y;
+        } else {
+            x = a.xyz[3 * p[k]];
+            y = a.xyz[3 * p[k] + 1];
+            z = a.xyz[3 * p[k] + 2];
+        }
+    };
     for (int64_t it = it_lo; it < it_hi; ++it) {
         const int e = (int)(it / a.kc);
         const int kk = (int)(it - (int64_t)e * a.kc);
@@ -376,10 +385,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         // this item's delays (samples) and Doppler shifts (Hz), Eq. (3)-(9) in FP64
-        double cD[kPPT], cnu[kPPT];
-#pragma unroll
-        for (int k = 0; k < kPPT; ++k)
-            pair_geometry(qx[k], qy[k], qz[k], a.states, a.n_rx, a.k0 + kk, pr, a.fs, a.inv_lambda, &cD[k], &cnu[k]);
         FactPoint pt[kPPT];
         int d0[kPPT];
         float th[kPPT];
@@ -387,8 +392,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         float tlo = FLT_MAX, thi = -FLT_MAX;
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
-            double D = cD[k];
-            const double nu = cnu[k];
+            double qx, qy, qz, D, nu;
+            point_ecef(k, qx, qy, qz);
+            pair_geometry(qx, qy, qz, a.states, a.n_rx, a.k0 + kk, pr, a.fs, a.inv_lambda, &D, &nu);
             // keep the integer lag representable whatever the geometry (NaN included)
             if (!(fabs(D) < 1.0e9)) D = 1.0e9;
             if constexpr (kMode == GEOLOC_DELAY_ROUND) {
@@ -505,7 +511,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         if (a.n_groups == 1)
             a.J[p[k]] = (float)jacc[k];
         else
-            a.partial[(int64_t)group * a.P + p[k]] = jacc[k];
+            a.partial[(int64_t)group * a.P + p[k]] = (float)jacc[k];
     }
 }
 
@@ -537,19 +543,17 @@ hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Items of at least this many samples (a step, or a segment of one) take the four-wave
-// budget in LINEAR mode; shorter ones pay its spills too often (on the 1e6-point map, steps
-// of 10,000 samples, it ran 2 % slower, while 250,000-sample steps ran 23 % faster).
-constexpr int64_t kLongItem = 32768;
-
 template <int kQMax, int kPPT, int kSub>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
-    constexpr int kW = kQMax > 4 ? 2 : (kSub == 4 ? 4 : 3);
+    // four cells per thread take three waves per SIMD too: the spills of that register budget
+    // (up to 216 bytes per lane) fall in the per-item set-up, none in the phase loops
+    constexpr int kW = kQMax > 4 ? 2 : (kPPT == 4 ? 3 : (kSub == 4 ? 4 : 3));
     if (delay_mode == GEOLOC_DELAY_ROUND) {
         hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
     } else if (delay_mode == GEOLOC_DELAY_SINC) {
-        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
+        if constexpr (kPPT < 4)
+            hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
     } else if constexpr (kW == 4) {
         const int64_t item = a.n_segs > 1 ? (int64_t)a.seg_len : (int64_t)a.L;
         if (item < kLongItem)
@@ -572,8 +576,13 @@ static void launch_fact_sub(const DirectArgs& a, uint8_t* deferred, int32_t dela
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s) {
     const int lanes = tile_lanes(a.tiling);
-    if ((lanes != 256 && lanes != 512) || (sub_blocks != 1 && sub_blocks != 4)) return hipErrorInvalidValue;
-    if (lanes == 512) {
+    if ((lanes != 256 && lanes != 512 && lanes != 1024) || (sub_blocks != 1 && sub_blocks != 4))
+        return hipErrorInvalidValue;
+    // 1024-cell tiles: LINEAR and ROUND with at most four Taylor terms
+    if (lanes == 1024 && (wide_doppler || delay_mode == GEOLOC_DELAY_SINC)) return hipErrorInvalidValue;
+    if (lanes == 1024) {
+        launch_fact_sub<kFQ, 4>(a, deferred, delay_mode, sub_blocks, s);
+    } else if (lanes == 512) {
         if (wide_doppler)
             launch_fact_sub<kFQWide, 2>(a, deferred, delay_mode, sub_blocks, s);
         else

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
     const int64_t p = tile_point(a.tiling, tile, lane, &valid);
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
-    if (valid && a.n_groups > 1 && a.mask) jacc = a.partial[(int64_t)group * a.P + p];
+    if (valid && a.n_groups > 1 && a.mask) jacc = (double)a.partial[(int64_t)group * a.P + p];
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
     if (a.n_groups == 1)
         a.J[p] = (float)jacc;
     else
-        a.partial[(int64_t)group * a.P + p] = jacc;
+        a.partial[(int64_t)group * a.P + p] = (float)jacc;
 }
 
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s) {

@@ -20,35 +20,64 @@ namespace geoloc {
 // the ellipsoid along its normal, with the prime-vertical radius N = a / sqrt(1 - e^2
 // sin^2 lat): x = (N + h) cos lat cos lon, y = (N + h) cos lat sin lon, z = (N (1 - e^2) +
 // h) sin lat. The height is alt (uniform) plus alt_p[p] when a per-point terrain is given.
-__global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ lat, const double* __restrict__ lon,
-                                                   int32_t grid_kind, int64_t rows, int64_t cols, int32_t model,
-                                                   double radius, double alt, const double* __restrict__ alt_p,
-                                                   double* __restrict__ xyz) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= rows * cols) return;
-    double la, lo;
-    if (grid_kind == GEOLOC_GRID_RECT) {
-        int64_t r = p / cols;
-        la = lat[r];
-        lo = lon[p - r * cols];
-    } else {
-        la = lat[p];
-        lo = lon[p];
-    }
-    const double h = alt + (alt_p ? alt_p[p] : 0.0);
+// The latitude part (A, Z) = ((N + h) cos lat, (N (1 - e^2) + h) sin lat) and the longitude
+// part (cos lon, sin lon) are formed separately and give x = A cos lon, y = A sin lon, z = Z.
+__device__ inline double2 ecef_lat_part(double la, double h, int32_t model, double radius) {
     const double cl = cos(la), sl = sin(la);
     if (model == GEOLOC_EARTH_WGS84) {
         const double a = kWgs84A, e2 = kWgs84F * (2.0 - kWgs84F);
         const double N = a / sqrt(1.0 - e2 * sl * sl);
-        xyz[3 * p + 0] = (N + h) * cl * cos(lo);
-        xyz[3 * p + 1] = (N + h) * cl * sin(lo);
-        xyz[3 * p + 2] = (N * (1.0 - e2) + h) * sl;
-    } else {
-        const double R = radius + h;
-        xyz[3 * p + 0] = R * cl * cos(lo);
-        xyz[3 * p + 1] = R * cl * sin(lo);
-        xyz[3 * p + 2] = R * sl;
+        return make_double2((N + h) * cl, (N * (1.0 - e2) + h) * sl);
     }
+    const double R = radius + h;
+    return make_double2(R * cl, R * sl);
+}
+
+__device__ inline double2 ecef_lon_part(double lo) { return make_double2(cos(lo), sin(lo)); }
+
+// Row and column factors of a rectilinear grid with a uniform height: row_tab[r] = the
+// latitude part of row r, col_tab[c] = the longitude part of column c.
+__global__ __launch_bounds__(256) void k_grid_ecef_factors(const double* __restrict__ lat, const double* __restrict__ lon,
+                                                           int64_t rows, int64_t cols, int32_t model, double radius,
+                                                           double alt, double2* __restrict__ row_tab,
+                                                           double2* __restrict__ col_tab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < rows)
+        row_tab[i] = ecef_lat_part(lat[i], alt, model, radius);
+    else if (i < rows + cols)
+        col_tab[i - rows] = ecef_lon_part(lon[i - rows]);
+}
+
+// ECEF of every point; a rectilinear grid with a uniform height takes the products of its
+// row and column factors (the same products the factored correlation kernel forms).
+__global__ __launch_bounds__(256) void k_grid_ecef(const double* __restrict__ lat, const double* __restrict__ lon,
+                                                   int32_t grid_kind, int64_t rows, int64_t cols, int32_t model,
+                                                   double radius, double alt, const double* __restrict__ alt_p,
+                                                   const double2* __restrict__ row_tab,
+                                                   const double2* __restrict__ col_tab, double* __restrict__ xyz) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= rows * cols) return;
+    double2 A, C;
+    if (row_tab) {
+        const int64_t r = p / cols;
+        A = row_tab[r];
+        C = col_tab[p - r * cols];
+    } else {
+        double la, lo;
+        if (grid_kind == GEOLOC_GRID_RECT) {
+            const int64_t r = p / cols;
+            la = lat[r];
+            lo = lon[p - r * cols];
+        } else {
+            la = lat[p];
+            lo = lon[p];
+        }
+        A = ecef_lat_part(la, alt + (alt_p ? alt_p[p] : 0.0), model, radius);
+        C = ecef_lon_part(lo);
+    }
+    xyz[3 * p + 0] = A.x * C.x;
+    xyz[3 * p + 1] = A.x * C.y;
+    xyz[3 * p + 2] = A.y;
 }
 
 // Points of whole tiles of a rectilinear grid, tile by tile (a POINTS plan's grid): point p
@@ -98,12 +127,19 @@ __global__ __launch_bounds__(256) void k_geometry(GeomArgs a) {
 }
 
 hipError_t launch_grid_ecef(const double* lat, const double* lon, int32_t grid_kind, int64_t rows, int64_t cols,
-                            int32_t model, double radius, double alt, const double* alt_p, double* xyz,
-                            hipStream_t s) {
+                            int32_t model, double radius, double alt, const double* alt_p, double2* row_tab,
+                            double2* col_tab, double* xyz, hipStream_t s) {
+    const bool factors = grid_kind == GEOLOC_GRID_RECT && !alt_p && row_tab && col_tab;
+    if (factors) {
+        hipLaunchKernelGGL(k_grid_ecef_factors, dim3((unsigned)((rows + cols + 255) / 256)), dim3(256), 0, s, lat, lon,
+                           rows, cols, model, radius, alt, row_tab, col_tab);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     int64_t P = rows * cols;
     dim3 grid((unsigned)((P + 255) / 256));
     hipLaunchKernelGGL(k_grid_ecef, grid, dim3(256), 0, s, lat, lon, grid_kind, rows, cols, model, radius, alt, alt_p,
-                       xyz);
+                       factors ? row_tab : nullptr, factors ? col_tab : nullptr, xyz);
     return hipGetLastError();
 }
 

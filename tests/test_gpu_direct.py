@@ -207,7 +207,7 @@ def test_factored_kernel_defers_wide_tiles(torch, G):
 
 
 def test_sheared_tiles_match_oracle(torch, G):
-    """On a 0.5 km grid the plan picks slanted (sheared) tiles of 256 or 512 cells that
+    """On a 0.5 km grid the plan picks slanted (sheared) tiles of 256 to 1024 cells that
     follow the lines of equal delay, at a slope of whole or fractional columns per row;
     which slope depends on the geometry, so two seeds with opposite gradient signs are
     mapped, LINEAR and SINC. All agree with the oracle over the whole grid."""
@@ -230,7 +230,7 @@ def test_sheared_tiles_match_oracle(torch, G):
         log(f"  err_J = {e:.3g}")
         assert e <= DIRECT_TOL
         check_argmax(Jg, Jo, DIRECT_TOL)
-    assert cells <= {256, 512}
+    assert cells <= {256, 512, 1024}
     assert any(sh != 0 for sh, _ in shears) and len({s for s, _ in shears}) >= 2
 
 
@@ -295,11 +295,14 @@ def test_step_segments(torch, G, delay, accum, spacing):
 
 @pytest.mark.parametrize("w,h,shear,tr,spacing,delay", [(16, 32, 0, 0, 8000.0, 0), (8, 64, 333, 1, 500.0, 0),
                                                         (4, 128, -700, 0, 500.0, 1), (32, 16, 150, 1, 8000.0, 1),
-                                                        (4, 64, -100, 0, 500.0, 2), (16, 16, 1024, 1, 2000.0, 2)])
+                                                        (4, 64, -100, 0, 500.0, 2), (16, 16, 1024, 1, 2000.0, 2),
+                                                        (8, 128, -318, 0, 500.0, 0), (32, 32, 200, 1, 2000.0, 1),
+                                                        (16, 64, 0, 0, 8000.0, 0)])
 def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
-    """Tilings the plan would not pick, fixed through geoloc_set_tiling: 512-cell tiles on 8 km
-    cells (most tile-steps deferred to the per-point kernel in two 256-lane halves), steep
-    and fractional shears, both orientations, SINC on 256-cell tiles; all match the oracle.
+    """Tilings the plan would not pick, fixed through geoloc_set_tiling: 512- and 1024-cell
+    tiles on 8 km cells (most tile-steps deferred to the per-point kernel in 256-lane
+    parts), 1024-cell tiles (four cells per thread) in LINEAR and ROUND, steep and
+    fractional shears, both orientations, SINC on 256-cell tiles; all match the oracle.
     Returning to the per-map choice works, and bad tilings are rejected."""
     wl = configs.MAP_1E6.with_(n_rows=45, n_cols=52, spacing_m=spacing, n_samples=30_000)
     scn = sim.make_scenario(wl, 60 + w + h + delay)
@@ -318,7 +321,8 @@ def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
         plan.set_tiling(0)
         J2 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
         assert err_J(J2, Jo) <= DIRECT_TOL
-        for bad in [(10, 10, 0, 0), (16, 16, 1025, 0), (16, 16, 0, 2)] + ([(16, 32, 0, 0)] if delay == 2 else []):
+        for bad in [(10, 10, 0, 0), (16, 16, 1025, 0), (16, 16, 0, 2), (32, 64, 0, 0)] + (
+                [(16, 32, 0, 0), (8, 128, 0, 0)] if delay == 2 else []):
             with pytest.raises(G.GeolocError) as ei:
                 plan.set_tiling(*bad)
             assert ei.value.status == G.EINVAL, bad
