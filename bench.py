@@ -146,6 +146,28 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     return flops, units, deferred, total
 
 
+def fma_ceiling(geoloc, torch, blocks: int = 2048, iters: int = 20000, reps: int = 3):
+    """Unpacked FP32 FMA rate of this device, from the library's probe kernel (16 independent
+    FMA chains per thread, eight workgroups per CU): the ceiling of an FP32 VALU kernel built
+    without the packed forms, measured at the clock the chip runs under that load."""
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    per_lane = geoloc.geoloc_fma_probe(blocks, iters, out.data_ptr(), stream)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        geoloc.geoloc_fma_probe(blocks, iters, out.data_ptr(), stream)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    fmas = blocks * 256 * per_lane
+    return {"tflops": round(2.0 * fmas / (best / 1e3) / 1e12, 2), "ms": round(best, 3),
+            "wave64_fma_per_cu_per_ns": round(fmas / 64 / 256 / (best * 1e6), 4), "blocks": blocks,
+            "fma_per_lane": per_lane}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -603,6 +625,8 @@ def main() -> int:
     ap.add_argument("--study-out", default="gpurun_out", help="directory of the per-scenario study records")
     ap.add_argument("--workers", type=int, default=16, help="CPU processes that simulate scenarios")
     ap.add_argument("--no-c3", action="store_true", help="skip the CAF-table error leg on the small inputs")
+    ap.add_argument("--no-fma-probe", action="store_true",
+                    help="skip the unpacked FP32 FMA ceiling measurement of the roofline")
     ap.add_argument("--continental", action="store_true",
                     help="also time the 4000 x 4000, 3-pair, 4e6-sample workload (direct and BF16 CAF, top-2)")
     ap.add_argument("--no-paper-scenario", action="store_true", help="skip the 58-capture scenario leg")
@@ -703,6 +727,11 @@ def main() -> int:
                                      / launches,
                 "pointwise_equivalent_tflops": round(FLOP_PER_UNIT_POINTWISE * units_per_launch / (k_ms / 1e3) / 1e12,
                                                      3)}
+
+    if not args.no_fma_probe:
+        log("unpacked FP32 FMA ceiling")
+        roofline["fma_ceiling"] = fma_ceiling(geoloc, torch)
+        roofline["frac_of_fma_ceiling"] = round(achieved / roofline["fma_ceiling"]["tflops"], 4)
 
     caf = None
     if not args.no_caf:

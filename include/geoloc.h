@@ -321,6 +321,17 @@ int geoloc_destroy(geoloc_plan_t plan);
 const char* geoloc_strerror(int status);
 const char* geoloc_last_error(void);
 
+/* Measurement helper, not a step of the method: the issue rate of unpacked FP32 FMA on the
+ * current device, the ceiling of the library's FP32 VALU kernels (which are compiled
+ * without the packed FP32 forms). Launches n_blocks workgroups of 256 threads, each thread
+ * running *fma_per_lane FMAs in 16 independent chains, asynchronously on
+ * `stream` (NULL = default); the caller times it (e.g. with events around the call) and
+ * divides n_blocks x 256 x *fma_per_lane by the time. out_dev: DEVICE float[n_blocks x 256]
+ * owned by the caller, receiving the chains' sums. *fma_per_lane (HOST) is set before the
+ * call returns. Errors: EINVAL (NULL pointer, n_blocks outside 1..2^20, iters outside
+ * 1..2^24), EDEVICE, ELAUNCH. */
+int geoloc_fma_probe(int32_t n_blocks, int32_t iters, float* out_dev, int64_t* fma_per_lane, void* stream);
+
 /* Sub-band split of complex captures (a DFT filter bank), the input of the learned tile
  * proposal's coarse map. Not a step of the paper's method: a coarse grid evaluated at
  * cell centres from full-band samples misses the one-sample-wide delay ridge of a

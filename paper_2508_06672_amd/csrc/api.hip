@@ -1412,6 +1412,18 @@ int geoloc_info(geoloc_plan_t p, geoloc_plan_info* out) {
     return GEOLOC_OK;
 }
 
+int geoloc_fma_probe(int32_t n_blocks, int32_t iters, float* out_dev, int64_t* fma_per_lane, void* stream) {
+    if (!out_dev || !fma_per_lane) return fail(GEOLOC_EINVAL, "geoloc_fma_probe: NULL pointer");
+    if (n_blocks < 1 || n_blocks > (1 << 20) || iters < 1 || iters > (1 << 24))
+        return fail(GEOLOC_EINVAL, "geoloc_fma_probe: n_blocks %d or iters %d out of range", n_blocks, iters);
+    int dev = 0;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    HIP_TRY(launch_fma_ceiling(n_blocks, iters, out_dev, (hipStream_t)stream));
+    *fma_per_lane = (int64_t)iters * fma_ceiling_chains();
+    return GEOLOC_OK;
+}
+
 int geoloc_subbands(const void* captures, int32_t n_ch, int64_t n_samples, int32_t n_bands, int32_t half_taps,
                     void* out, void* stream) {
     if (captures == nullptr || out == nullptr) return fail(GEOLOC_EINVAL, "geoloc_subbands: null buffer");

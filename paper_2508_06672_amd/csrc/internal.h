@@ -273,6 +273,10 @@ constexpr int kMaxTopK = 64;
 constexpr int kArgmaxMaxBlocks = 1024;   // most block partials of one argmax pass
 hipError_t launch_argmax(const float* J, int64_t P, int64_t cols, int32_t rect, int32_t radius, int32_t top_k,
                          ArgmaxScratch& s, hipStream_t st);
+// measurement helper (k_calib.hip): n_blocks x 256 threads of independent FP32 FMA chains,
+// fma_ceiling_chains() x iters FMAs per thread; out holds n_blocks x 256 floats
+hipError_t launch_fma_ceiling(int32_t n_blocks, int32_t iters, float* out, hipStream_t s);
+int32_t fma_ceiling_chains();
 // Record a detail string for geoloc_last_error() and return code.
 int set_last_error(int code, const char* msg);
 int32_t argmax_blocks(int64_t P);

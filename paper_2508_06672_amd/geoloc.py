@@ -116,9 +116,10 @@ def load() -> ctypes.CDLL:
     lib.geoloc_cfar_scale.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
     lib.geoloc_argmax_noalloc.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_float), _vp]
+    lib.geoloc_fma_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, P(ctypes.c_int64), _vp]
     for name in ("geoloc_plan", "geoloc_set_timing", "geoloc_set_grid", "geoloc_map", "geoloc_geometry", "geoloc_caf_table", "geoloc_argmax",
                  "geoloc_detect", "geoloc_set_tiling", "geoloc_set_taylor_block", "geoloc_set_points_from_tiles", "geoloc_info", "geoloc_destroy",
-                 "geoloc_subbands", "geoloc_cfar_scale", "geoloc_argmax_noalloc"):
+                 "geoloc_subbands", "geoloc_cfar_scale", "geoloc_argmax_noalloc", "geoloc_fma_probe"):
         getattr(lib, name).restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.geoloc_cnn_create.argtypes = [P(geoloc_cnn_desc), P(_vp)]
@@ -232,6 +233,14 @@ def geoloc_cfar_scale(pfa: float, n_train: int, looks: int = 1) -> float:
     out = ctypes.c_double(0.0)
     _check(load().geoloc_cfar_scale(float(pfa), int(n_train), int(looks), ctypes.byref(out)), "geoloc_cfar_scale")
     return out.value
+
+
+def geoloc_fma_probe(n_blocks: int, iters: int, out_ptr: int, stream: int = 0) -> int:
+    """Launch the library's FP32 FMA issue-rate probe; returns the FMAs each lane runs."""
+    n = ctypes.c_int64(0)
+    _check(load().geoloc_fma_probe(int(n_blocks), int(iters), ctypes.c_void_p(out_ptr), ctypes.byref(n),
+                                   ctypes.c_void_p(stream)), "geoloc_fma_probe")
+    return n.value
 
 
 def cfar_scale(pfa: float, n_train: int, looks: int = 1) -> float:

@@ -172,3 +172,13 @@ def test_cfar_scale_rejects_bad_arguments(args):
     assert lib.geoloc_cfar_scale(*args, ctypes.byref(out)) == geoloc.EINVAL
     assert out.value == -7.0
     assert lib.geoloc_cfar_scale(1e-3, 10, 1, None) == geoloc.EINVAL
+
+
+def test_fma_probe_validation_returns_einval():
+    """The FP32 FMA probe checks its arguments before any device call."""
+    lib = geoloc.load()
+    buf = ctypes.c_void_p(4096)          # never dereferenced: each call fails validation first
+    n = ctypes.c_int64(0)
+    for args in [(0, 100, buf, ctypes.byref(n)), (1 << 21, 100, buf, ctypes.byref(n)), (8, 0, buf, ctypes.byref(n)),
+                 (8, 1 << 25, buf, ctypes.byref(n)), (8, 100, None, ctypes.byref(n)), (8, 100, buf, None)]:
+        assert lib.geoloc_fma_probe(*args, None) == geoloc.EINVAL, args
