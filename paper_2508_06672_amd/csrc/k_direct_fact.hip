@@ -48,6 +48,9 @@ constexpr int kFQWide = 6;       // most Taylor terms of the variant for wide Do
 constexpr int kFH = 128;         // most lags per tile and step (spread + 2)
 constexpr int kFVS = kFB + 2;    // LDS stride of the reference samples of one block
 constexpr float kFTol = 5.9604645e-8f;   // Taylor remainder bound: 2^-24 of the block magnitude sum
+// LDS tiles between exact re-anchorings of the block recurrence (at most 80 Taylor blocks of
+// 256 samples: its rounding grows with the blocks between anchors, a few 1e-6 at most)
+constexpr int kAnchorTiles = 8;
 
 // Workgroup min / max of two ints and two floats (wave shuffles, then LDS; the barrier
 // before the LDS writes keeps them clear of the previous call's reads).
@@ -167,8 +170,8 @@ struct FactPoint {
 // The moments of a round sit lag-major, s_G[(block * Hs + lag) * Q + q], so that a point
 // reads the 2Q (LINEAR) or 8Q (SINC) values of its lags from one base address. Per block a
 // point forms s_b = sum_q a_q m_q and folds it into acc = acc conj(E) + s_b (E = e^{j theta_p
-// B}, Horner's rule for sum_b E^b s_b); at the end of an LDS tile acc times the exact FP64
-// weight of the tile's last block goes into C. For LINEAR the interpolation weights are
+// B}, Horner's rule for sum_b E^b s_b); every kAnchorTiles LDS tiles and at the end of the
+// step acc times the exact FP64 weight of the last block goes into C. For LINEAR the interpolation weights are
 // folded into the Taylor coefficients once per step: a_q m_q = ((1 - a) a_q) G_q(d0) +
 // (a a_q) G_q(d0 + 1), four FMAs per Taylor term and block.
 // s_G seen through the LDS address space as 8-byte vectors: the phase-2 reads must be
@@ -199,6 +202,10 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
                 cf[k][0][q] = pt[k].c[q];
             }
         }
+    float accr[kPPT], acci[kPPT];   // sum_b conj(E)^(last - b) s_b since the last anchor
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k) accr[k] = acci[k] = 0.f;
+    int tiles_since = 0;
     for (int s0 = st.seg_lo; s0 < st.seg_hi; s0 += st.TB * kLB) {
         const int tl = min(st.TB * kLB, st.seg_hi - s0);
         const int nblk = (tl + kLB - 1) / kLB;     // long blocks
@@ -227,9 +234,6 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
             }
         }
         __syncthreads();
-        float accr[kPPT], acci[kPPT];   // sum_b conj(E)^(last - b) s_b over this LDS tile
-#pragma unroll
-        for (int k = 0; k < kPPT; ++k) accr[k] = acci[k] = 0.f;
         for (int bb = 0; bb < nblk; bb += st.NB) {
             // phase 1: item (my_b, my_l, my_s) forms the moments of sub-block my_s of long block
             // bb + my_b at lags my_l, my_l + 1; the kSub lanes of a long block (a quad, when
@@ -305,13 +309,19 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
             }
             __syncthreads();
         }
-        // the exact weight of the tile's last block turns acc into this tile's share of C
-        const double t_last = (double)s0 + (double)(nblk - 1) * kLB + 0.5 * (double)(kLB - 1) - centre;
+        // every kAnchorTiles LDS tiles and at the end of the step (or segment) the exact FP64
+        // weight of the last block turns acc into its share of C; in between the recurrence
+        // runs on across the tiles (uniform over the workgroup)
+        if (++tiles_since == kAnchorTiles || s0 + st.TB * kLB >= st.seg_hi) {
+            const double t_last = (double)s0 + (double)(nblk - 1) * kLB + 0.5 * (double)(kLB - 1) - centre;
 #pragma unroll
-        for (int k = 0; k < kPPT; ++k) {
-            const float2 W = cis_cycles(pt[k].cyc * t_last);
-            cr[k] = fmaf(W.x, accr[k], fmaf(-W.y, acci[k], cr[k]));
-            ci[k] = fmaf(W.x, acci[k], fmaf(W.y, accr[k], ci[k]));
+            for (int k = 0; k < kPPT; ++k) {
+                const float2 W = cis_cycles(pt[k].cyc * t_last);
+                cr[k] = fmaf(W.x, accr[k], fmaf(-W.y, acci[k], cr[k]));
+                ci[k] = fmaf(W.x, acci[k], fmaf(W.y, accr[k], ci[k]));
+                accr[k] = acci[k] = 0.f;
+            }
+            tiles_since = 0;
         }
     }
 }
