@@ -158,8 +158,8 @@ struct FactPoint {
     float2 ERB;            // exp(j 2 pi cyc B): the block weight's step
     float alpha;           // fractional lag
     float w[kSincTaps];    // windowed-sinc weights (SINC only)
-    float c[kFQWide];      // Taylor coefficients of the Doppler deviation: |(j delta)^q / q!|
-                           // with the sign of j^q's nonzero part
+    float dl;              // Doppler deviation from the tile's mean (radians per sample): the
+                           // Taylor coefficients are formed from it where the order is known
     int off;               // lag offset of the first lag read in s_G
 };
 
@@ -187,20 +187,25 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
     constexpr int kLB = kSub * kFB;
     const double centre = 0.5 * (double)(a.L - 1);
     const int Hs = st.Hs;
-    // per-point coefficients of the lags the point reads (see above)
+    // per-point coefficients of the lags the point reads (see above): the Taylor coefficients
+    // |(j dl)^q / q!| with the sign of j^q's nonzero part (j^q is 1, j, -1, -j in turn)
     constexpr int kT = kMode == GEOLOC_DELAY_LINEAR ? 2 : 1;
     float cf[kPPT][kT][Q];
 #pragma unroll
-    for (int k = 0; k < kPPT; ++k)
+    for (int k = 0; k < kPPT; ++k) {
+        float t = 1.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
+            const float c = (q & 2) ? -t : t;
+            t *= pt[k].dl * (1.f / (float)(q + 1));
             if constexpr (kMode == GEOLOC_DELAY_LINEAR) {
-                cf[k][0][q] = (1.f - pt[k].alpha) * pt[k].c[q];
-                cf[k][1][q] = pt[k].alpha * pt[k].c[q];
+                cf[k][0][q] = (1.f - pt[k].alpha) * c;
+                cf[k][1][q] = pt[k].alpha * c;
             } else {
-                cf[k][0][q] = pt[k].c[q];
+                cf[k][0][q] = c;
             }
         }
+    }
     float accr[kPPT], acci[kPPT];   // sum_b conj(E)^(last - b) s_b since the last anchor
 #pragma unroll
     for (int k = 0; k < kPPT; ++k) accr[k] = acci[k] = 0.f;
@@ -474,14 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         for (int k = 0; k < kPPT; ++k) {
             pt[k].ERB = cis_cycles(pt[k].cyc * (double)kLB);
             if constexpr (kMode == GEOLOC_DELAY_SINC) sinc_taps(pt[k].alpha, pt[k].w);
-            // (j dl)^q / q! = j^q dl^q / q!: j^q is 1, j, -1, -j in turn
-            const float dl = (float)(two_pi * pt[k].cyc - (double)tbar);
-            float t = 1.f;
-#pragma unroll
-            for (int q = 0; q < kFQWide; ++q) {
-                pt[k].c[q] = ((q & 2) ? -t : t);
-                t *= dl * (1.f / (float)(q + 1));
-            }
+            pt[k].dl = (float)(two_pi * pt[k].cyc - (double)tbar);
             pt[k].off = valid[k] ? d0[k] - dlo : 0;
         }
         st.dlo = dlo - kTapLo;
