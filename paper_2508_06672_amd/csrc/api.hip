@@ -313,7 +313,7 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // block's centre and summed) cut the per-point share fourfold but need more Taylor terms
 // for the same Doppler spread; both block lengths are priced. A tiling whose launch has
 // fewer than 768 workgroups (three per CU) is charged for the idle share of the chip, and
-// SINC keeps to 256-cell tiles at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
+// SINC keeps to tiles of 256 or 512 cells at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
 // are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
 // Tiles of 1024 cells (four per thread, LINEAR and ROUND, at most four Taylor terms) share
@@ -466,10 +466,11 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     }
     if (p->tiling_fixed) return;
     for (const auto& shape : p->tile_shapes) {
-        // the SINC combination is bound by per-point work, registers and LDS reads: 256-cell
-        // tiles at most 8 cells wide (on the 1e6-point map 16-wide tiles ran 1.4x slower,
-        // each wave's cells reading twice as many distinct lags per block)
-        if (p->delay_mode == GEOLOC_DELAY_SINC && (tile_lanes(shape) != kTilePoints || shape.tile_w > 8)) continue;
+        // the SINC combination is bound by per-point work, registers and LDS reads: tiles of
+        // 256 or 512 cells at most 8 cells wide (on the 1e6-point map 16-wide tiles ran 1.4x
+        // slower, each wave's cells reading twice as many distinct lags per block; 8 x 64 took
+        // 23.4 ms against 30.8 ms on 4 x 64)
+        if (p->delay_mode == GEOLOC_DELAY_SINC && (tile_lanes(shape) > 512 || shape.tile_w > 8)) continue;
         // shears: whole columns per row, and the slope of each pair's lines of equal delay
         std::vector<int32_t> shears = {-2 * kShearOne, -kShearOne, 0, kShearOne, 2 * kShearOne};
         for (const auto& g : grads) {
@@ -1072,8 +1073,8 @@ int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t s
     const int64_t cells = (int64_t)tile_w * tile_h;
     if (tile_w < 1 || tile_h < 1 || (cells != 256 && cells != 512 && cells != 1024))
         return fail(GEOLOC_EINVAL, "tile must hold 256, 512 or 1024 cells (got %d x %d)", tile_w, tile_h);
-    if (cells != kTilePoints && p->delay_mode == GEOLOC_DELAY_SINC)
-        return fail(GEOLOC_EINVAL, "SINC takes 256-cell tiles");
+    if (cells > 512 && p->delay_mode == GEOLOC_DELAY_SINC)
+        return fail(GEOLOC_EINVAL, "SINC takes tiles of 256 or 512 cells");
     if (shear < -kMaxShear || shear > kMaxShear) return fail(GEOLOC_EINVAL, "|shear| must be <= %d", kMaxShear);
     if (transpose != 0 && transpose != 1) return fail(GEOLOC_EINVAL, "transpose must be 0 or 1");
     PointTiling t = p->base_tiling;

@@ -297,12 +297,12 @@ def test_step_segments(torch, G, delay, accum, spacing):
                                                         (4, 128, -700, 0, 500.0, 1), (32, 16, 150, 1, 8000.0, 1),
                                                         (4, 64, -100, 0, 500.0, 2), (16, 16, 1024, 1, 2000.0, 2),
                                                         (8, 128, -318, 0, 500.0, 0), (32, 32, 200, 1, 2000.0, 1),
-                                                        (16, 64, 0, 0, 8000.0, 0)])
+                                                        (16, 64, 0, 0, 8000.0, 0), (8, 64, -318, 0, 500.0, 2)])
 def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
     """Tilings the plan would not pick, fixed through geoloc_set_tiling: 512- and 1024-cell
     tiles on 8 km cells (most tile-steps deferred to the per-point kernel in 256-lane
     parts), 1024-cell tiles (four cells per thread) in LINEAR and ROUND, steep and
-    fractional shears, both orientations, SINC on 256-cell tiles; all match the oracle.
+    fractional shears, both orientations, SINC on 256- and 512-cell tiles; all match the oracle.
     Returning to the per-map choice works, and bad tilings are rejected."""
     wl = configs.MAP_1E6.with_(n_rows=45, n_cols=52, spacing_m=spacing, n_samples=30_000)
     scn = sim.make_scenario(wl, 60 + w + h + delay)
@@ -322,7 +322,7 @@ def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
         J2 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
         assert err_J(J2, Jo) <= DIRECT_TOL
         for bad in [(10, 10, 0, 0), (16, 16, 1025, 0), (16, 16, 0, 2), (32, 64, 0, 0)] + (
-                [(16, 32, 0, 0), (8, 128, 0, 0)] if delay == 2 else []):
+                [(8, 128, 0, 0), (32, 32, 0, 0)] if delay == 2 else []):
             with pytest.raises(G.GeolocError) as ei:
                 plan.set_tiling(*bad)
             assert ei.value.status == G.EINVAL, bad
