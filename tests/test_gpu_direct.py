@@ -362,20 +362,22 @@ def test_taylor_blocks_match_oracle(torch, G, block, delay, spacing, step):
         assert err_J(J2, Jo) <= DIRECT_TOL
 
 
-def test_random_tilings_on_ragged_grids(torch, G):
-    """Twenty seeded random tilings (shape, shear in 1/256 column per row, orientation) on
-    grids of odd sizes, some narrower than a tile: every cell is covered exactly once and
-    the map matches the oracle."""
-    rng = np.random.Generator(np.random.PCG64(77))
-    shapes = [(16, 16), (8, 32), (4, 64), (32, 8), (64, 4), (16, 32), (8, 64), (4, 128), (32, 16), (128, 4)]
+@pytest.mark.parametrize("seed,n_cases,shapes", [
+    (77, 20, [(16, 16), (8, 32), (4, 64), (32, 8), (64, 4), (16, 32), (8, 64), (4, 128), (32, 16), (128, 4)]),
+    (78, 10, [(32, 32), (16, 64), (64, 16), (8, 128), (128, 8), (4, 256), (256, 4)])])
+def test_random_tilings_on_ragged_grids(torch, G, seed, n_cases, shapes):
+    """Seeded random tilings (shape, shear in 1/256 column per row, orientation) on grids of
+    odd sizes, some narrower than a tile, with one or two cells per thread, and with four
+    (1024-cell tiles): every cell is covered exactly once and the map matches the oracle."""
+    rng = np.random.Generator(np.random.PCG64(seed))
     wl0 = configs.MAP_1E6.with_(n_samples=20_000, step_len=10_000)
-    for case in range(20):
+    for case in range(n_cases):
         rows, cols = int(rng.integers(3, 70)), int(rng.integers(3, 70))
         w, h = shapes[int(rng.integers(len(shapes)))]
         shear = int(rng.integers(-1024, 1025))
         tr = int(rng.integers(2))
         wl = wl0.with_(n_rows=rows, n_cols=cols, spacing_m=float(rng.choice([500.0, 2000.0])))
-        scn = sim.make_scenario(wl, 500 + case)
+        scn = sim.make_scenario(wl, 500 + case + 100 * (seed - 77))
         Jo = oracle.map_scenario(scn)
         caps = torch.from_numpy(scn.captures).cuda()
         with G.Plan.for_scenario(scn) as plan:
