@@ -7,8 +7,8 @@
 //   D = (tau_j - tau_i) f_s,   nu = f_j - f_i.
 // Both kernels evaluate every product and sum as written (no contraction into FMA), which
 // keeps them within a few units in the last place of a plain FP64 implementation of the
-// same expressions (the geometry takes 1/rho once; the device's sqrt and sincos round
-// differently).
+// same expressions (the geometry forms 1/rho by a reciprocal square root refined by Newton
+// steps and rho as rr / rho; the device's sincos rounds differently).
 #include "internal.h"
 
 namespace geoloc {
