@@ -622,7 +622,7 @@ def main() -> int:
     ap.add_argument("--study", action="store_true",
                     help="the full agreement study: 1000 CAF seeds and 300 learned-proposal seeds, with "
                          "per-scenario records written under --study-out")
-    ap.add_argument("--study-out", default="gpurun_out", help="directory of the per-scenario study records")
+    ap.add_argument("--study-out", default="study_records", help="directory of the per-scenario study records")
     ap.add_argument("--workers", type=int, default=16, help="CPU processes that simulate scenarios")
     ap.add_argument("--no-c3", action="store_true", help="skip the CAF-table error leg on the small inputs")
     ap.add_argument("--no-fma-probe", action="store_true",
