@@ -512,6 +512,7 @@ def continental_leg(geoloc, torch, seed: int = 0):
         with geoloc.Plan.for_scenario(scn, **kw) as plan:
             J = plan.map(caps, scn.states)
             torch.cuda.synchronize()
+            plan.set_timing(True)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             plan.map(caps, scn.states, J=J)
@@ -519,9 +520,16 @@ def continental_leg(geoloc, torch, seed: int = 0):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
+            info = plan.info()
             peaks[name] = [int(p) for p in pk]
             out[name] = {"map_ms": ms, "value": wl.units / (ms / 1e3), "top2": peaks[name],
-                         "top2_vals": [float(v) for v in pv]}
+                         "top2_vals": [float(v) for v in pv],
+                         "kernel_ms": {"geometry": info["geometry_ms"], "correlate": info["correlate_ms"],
+                                       "pointwise_pass": info["interp_ms"]}}
+            if name == "direct_fp32":
+                out[name]["tile"] = (f"{info['tile_rows']}x{info['tile_cols']} shear {info['tile_shear'] / 256:+.3f}"
+                                     f"{' transposed' if info['tile_transpose'] else ''}")
+                out[name]["taylor_block"] = info["taylor_block"]
             log(f"  continental {name}: {ms:.1f} ms, top-2 {peaks[name]}")
     # the combined form: the learned proposal (network trained on the 1024 x 1024 proposal
     # workload, applied to the 250 x 250 tiles of this grid), falling back to the BF16 CAF map

@@ -87,7 +87,8 @@ struct geoloc_plan_s {
     double* d_lon = nullptr;
     double* d_states = nullptr;
     int2* d_pairs = nullptr;
-    uint32_t* d_defer_flags = nullptr;   // [step chunks] deferral flag of each correlation launch
+    uint32_t* d_defer_flags = nullptr;   // [2][step chunks] deferral flags of the two factored passes
+    int64_t n_chunks = 0;                // step chunks (correlation launches per map)
     uint32_t defer_seq = 0;              // sequence number of the current map (never 0)
     float* d_partial = nullptr;      // [item groups][P]: small grids, or the balanced split of a large one
     int32_t n_groups = 1;            // item groups of a grid too small to fill the GPU
@@ -927,6 +928,7 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
     if (kc > p->K) kc = p->K;
     const int64_t n_chunks = (p->K + kc - 1) / kc;
     p->kc = (int32_t)((p->K + n_chunks - 1) / n_chunks);
+    p->n_chunks = n_chunks;
 
     do {
         if ((rc = dev_alloc(p, &p->d_xyz, (size_t)P * 3))) break;
@@ -936,8 +938,8 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
             break;
         if ((rc = dev_alloc(p, &p->d_states, (size_t)p->K * p->n_rx * 6))) break;
         if ((rc = dev_alloc(p, &p->d_pairs, pairs.size()))) break;
-        if ((rc = dev_alloc(p, &p->d_defer_flags, (size_t)n_chunks))) break;
-        if (hipMemset(p->d_defer_flags, 0, (size_t)n_chunks * sizeof(uint32_t)) != hipSuccess) {
+        if ((rc = dev_alloc(p, &p->d_defer_flags, (size_t)(2 * n_chunks)))) break;
+        if (hipMemset(p->d_defer_flags, 0, (size_t)(2 * n_chunks) * sizeof(uint32_t)) != hipSuccess) {
             rc = fail(GEOLOC_ELAUNCH, "hipMemset failed");
             break;
         }
@@ -968,8 +970,9 @@ int geoloc_plan(const geoloc_desc* d, geoloc_plan_t* out) {
                 (rc = dev_alloc(p, &p->d_partial, (size_t)p->max_balance_groups * P)))
                 break;
         }
+        // (whole 32-bit words: the second pass clears bits with word atomics)
         if (p->use_fact &&
-            (rc = dev_alloc(p, &p->d_deferred, (size_t)p->n_pairs * p->kc * p->max_tiles)))
+            (rc = dev_alloc(p, &p->d_deferred, ((size_t)p->n_pairs * p->kc * p->max_tiles + 3) & ~(size_t)3)))
             break;
         p->am.n_blocks = argmax_blocks(P);
         if ((rc = dev_alloc(p, &p->am.part_val, p->am.n_blocks))) break;
@@ -1178,12 +1181,27 @@ int geoloc_map(geoloc_plan_t p, const geoloc_inputs* in, float* J, uint32_t flag
         if ((rc = span_end(p, s, &sc))) return rc;
         if (p->timing) p->correlate_launches++;
         if (p->use_fact) {
-            // the per-point kernel adds the (tile, step) pairs the factored kernel deferred
             TimedSpan sd{};
             DirectArgs m = a;
             m.mask = p->d_deferred;
             m.load_J = 1;
             if ((rc = span_begin(p, s, &sd, 2))) return rc;
+            const int parts = tile_lanes(a.tiling) / 256;
+            if (p->fact_sub == 4 || parts > 1) {
+                // the deferred (tile, step) pairs go through the factored kernel again in
+                // 256-cell parts of the tile (a part spans fewer lags) with 64-sample Taylor
+                // blocks (a quarter of the Doppler phase spread over a block) and up to six
+                // terms; the parts it defers again fall to the per-point kernel, gated on this
+                // pass's flag. Whole steps: after a segment reduction J holds the rest.
+                DirectArgs b = m;
+                b.parts = parts;
+                b.n_segs = 1;
+                b.gate_flag = a.defer_flag;
+                b.defer_flag = a.defer_flag + p->n_chunks;
+                HIP_TRY(launch_direct_fact(b, p->d_deferred, p->delay_mode, true, 1, s));
+                m.defer_flag = b.defer_flag;
+            }
+            // the per-point kernel adds the (tile, step) pairs the factored kernel deferred
             if (p->delay_mode == GEOLOC_DELAY_SINC)
                 HIP_TRY(launch_direct_sinc(m, s));
             else

@@ -87,18 +87,45 @@ struct DirectArgs {
     int32_t load_J;          // add onto the existing J values
     int32_t n_groups;        // groups of (pair, step) items per chunk (1: each workgroup owns its points' J)
     float* partial;          // [n_groups][P] partial sums when n_groups > 1
-    const uint8_t* mask;     // [n_pairs][kc][n_tiles]: nonzero = this kernel handles it; NULL = all
+    // [n_pairs][kc][n_tiles] deferral bytes, bit h for the tile's 256-cell part h (cells
+    // 256 h .. 256 h + 255 of the tile): set = this pass handles that part; NULL = all
+    const uint8_t* mask;
     // deferral flag of this launch: the factored kernel stores defer_seq into *defer_flag
-    // when it leaves any (tile, step) to the per-point kernel, whose masked pass returns at
-    // once unless the flag holds defer_seq (a per-map sequence number, so the flag never
-    // needs clearing)
+    // when it leaves any (tile, step) to a later pass, which returns at once unless the
+    // flag holds defer_seq (a per-map sequence number, so the flag never needs clearing)
     uint32_t* defer_flag;
     uint32_t defer_seq;
+    // factored kernel with a mask (a second pass, over the (tile, step) pairs the first
+    // pass deferred, with shorter Taylor blocks and tiles cut into parts): returns at once
+    // unless *gate_flag (the first pass's flag) holds defer_seq; adds only the flagged
+    // parts, clears the bits of those it completes and raises its own defer_flag for
+    // those it defers again
+    const uint32_t* gate_flag;
+    // factored kernel with a mask: workgroups per tile, each taking tile_lanes / parts
+    // consecutive cells (256); without a mask always one
+    int32_t parts;
     // factored kernel only: each step split into n_segs coherent segments of seg_len samples
     // (a multiple of 64) whose complex sums go to cpart [n_segs][n_pairs * kc][P]; 1 = off
     int32_t n_segs, seg_len;
     float2* cpart;
 };
+
+// Masked passes: the first item at or after `it` and below it_hi whose deferral byte for
+// `tile` has any of `bits` set, or it_hi if none. A wave reads the bytes of 64 items at once
+// (lane l that of item base + l, base a multiple of 64) and takes the first set bit of their
+// ballot, instead of one dependent byte read per item. Every lane of the wave must be active
+// and pass the same arguments; the result is the same in every wave of the workgroup.
+__device__ inline int64_t next_flagged(const uint8_t* mask, int64_t n_tiles, int64_t tile, uint32_t bits, int64_t it,
+                                       int64_t it_hi) {
+    const int lane = (int)(threadIdx.x & 63);
+    while (it < it_hi) {
+        const int64_t j = (it & ~(int64_t)63) + lane;
+        const unsigned long long w = __ballot(j >= it && j < it_hi && (mask[j * n_tiles + tile] & bits) != 0);
+        if (w) return (it & ~(int64_t)63) + __builtin_ctzll(w);
+        it = (it & ~(int64_t)63) + 64;
+    }
+    return it_hi;
+}
 
 // exp(j 2 pi cyc) with the argument reduced in FP64 and evaluated in FP32.
 __device__ inline float2 cis_cycles(double cyc) {
@@ -145,7 +172,8 @@ __device__ inline void sinc_taps(float alpha, float (&w)[kSincTaps]) {
     for (int t = 0; t < kSincTaps; ++t) w[t] *= inv;
 }
 
-// sub_blocks: 64-sample sub-blocks per Taylor block, 1 or 4
+// sub_blocks: 64-sample sub-blocks per Taylor block, 1 or 4; a tile of 256, 512 or 1024
+// cells. With a mask: a.parts workgroups of 256 cells per tile and sub_blocks 1.
 hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s);
 hipError_t launch_direct_sinc(const DirectArgs& a, hipStream_t s);

@@ -137,7 +137,8 @@ void k_direct(DirectArgs a) {
     const int halves = tile_lanes(a.tiling) / 256;
     const int64_t sub = blockIdx.x % (a.n_tiles * halves);
     const int64_t tile = sub / halves;
-    const int lane = (int)(sub - tile * halves) * 256 + tid;
+    const int half = (int)(sub - tile * halves);
+    const int lane = half * 256 + tid;
     const int group = (int)(blockIdx.x / (a.n_tiles * halves));
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
@@ -151,14 +152,18 @@ void k_direct(DirectArgs a) {
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
+        // with a mask, only this 256-cell part of the (tile, step) pairs the factored kernel
+        // left over
+        if (a.mask) {
+            it = next_flagged(a.mask, a.n_tiles, tile, 1u << half, it, it_hi);
+            if (it >= it_hi) break;
+        }
         const int e = (int)(it / a.kc);
         const int kk = (int)(it - (int64_t)e * a.kc);
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;
         {
-            // with a mask, only the (tile, step) pairs the factored kernel left over
-            if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
             const int64_t n_step = (int64_t)(a.k0 + kk) * a.L;
             // delay (samples) and Doppler shift (Hz) of this point, Eq. (3)-(9) in FP64
             double D = 0.0, nu = 0.0;

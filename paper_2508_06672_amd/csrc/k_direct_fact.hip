@@ -16,7 +16,7 @@
 //   a_q(p) = (j delta_p)^q / q!,   G_q(b, d) = sum_{r in b} r^q x[n] e^{j theta_bar r} conj(y_j[n + d]).
 //
 // The moments G_q(b, d) depend on the lag only, not on the point, so a tile computes them
-// once for its dozen or so lags and every point combines 2Q of them per block (ROUND: Q;
+// once for its 10 to 20 or so lags and every point combines 2Q of them per block (ROUND: Q;
 // the eight-tap SINC delay: 8Q) by Horner's rule over the blocks. The moment work is
 // spread over the workgroup as (block, lag pair) items, floor(256 / ceil(H / 2)) blocks
 // per round, so that few lanes idle whatever the tile's lag spread H; the two lags of a
@@ -27,7 +27,10 @@
 // block's magnitude sum, below the rounding of the block sum itself; a tile whose lag
 // spread exceeds kFH or whose Doppler spread needs more Taylor terms than the variant
 // carries (4, or 6 in the variant the host picks for wide Doppler spreads) is flagged in
-// `deferred` and left to the per-point kernel, which then adds that step into J.
+// `deferred`. A second, masked launch takes the flagged (tile, step) pairs again in 256-cell
+// parts of the tile (a quarter of a 1024-cell tile spans about a quarter of its lags) with
+// 64-sample blocks and up to 6 terms, and adds them into J; the per-point kernel adds the
+// parts that still do not fit.
 #include "internal.h"
 
 #include <cfloat>
@@ -330,6 +333,13 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
     }
 }
 
+// Clears bits of the deferral byte at flag with an atomic AND on its aligned 32-bit word (the
+// workgroups of a tile's parts share the byte; the mask allocation is padded to whole words).
+__device__ inline void clear_deferral_bits(uint8_t* flag, uint32_t bits) {
+    const uintptr_t ad = (uintptr_t)flag;
+    atomicAnd((unsigned int*)(ad & ~(uintptr_t)3), ~(bits << (8u * (unsigned)(ad & 3))));
+}
+
 // kMode: GEOLOC_DELAY_LINEAR, _ROUND or _SINC; kQMax: most Taylor terms; kPPT: points per
 // thread (tiles of 256 kPPT cells: 1, 2, or 4 for LINEAR and ROUND); kSub: 64-sample
 // sub-blocks per Taylor block (1 or 4); kWaves: waves per SIMD the register budget is set
@@ -350,9 +360,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
     __shared__ float s_f[2][4];
 
     const int tid = threadIdx.x;
-    // workgroup -> (point tile, group of (pair, step) items, segment of the step)
-    const int64_t tile = blockIdx.x % a.n_tiles;
-    const int gs = (int)(blockIdx.x / a.n_tiles);
+    // a pass over the tile-steps that an earlier factored launch deferred (a.mask set; only
+    // the variant with one cell per thread and 64-sample blocks takes one): it has nothing to
+    // do unless that launch flagged some (uniform over the workgroup)
+    constexpr bool kMaskable = kPPT == 1 && kSub == 1;
+    const bool masked = kMaskable && a.mask != nullptr;
+    if (masked && *a.gate_flag != a.defer_seq) return;
+    // workgroup -> (point tile, part of the tile, group of (pair, step) items, segment of
+    // the step)
+    const int64_t parts = masked ? a.parts : 1;
+    const int64_t tile_parts = a.n_tiles * parts;
+    const int64_t tp = blockIdx.x % tile_parts;
+    const int64_t tile = tp / parts;
+    const int part = (int)(tp - tile * parts);
+    const int gs = (int)(blockIdx.x / tile_parts);
+    // deferral bits of the 256-cell parts of the tile this workgroup covers
+    const uint32_t my_bits = ((1u << kPPT) - 1u) << (part * kPPT);
     const int group = gs % a.n_groups;
     const int seg = gs / a.n_groups;
     const bool segmented = a.n_segs > 1;
@@ -364,8 +387,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
     double jacc[kPPT];
 #pragma unroll
     for (int k = 0; k < kPPT; ++k) {
-        p[k] = tile_point(a.tiling, tile, tid + 256 * k, &valid[k]);
-        jacc[k] = (valid[k] && a.load_J && a.n_groups == 1) ? (double)a.J[p[k]] : 0.0;
+        p[k] = tile_point(a.tiling, tile, part * 256 * kPPT + tid + 256 * k, &valid[k]);
+        jacc[k] = (valid[k] && a.load_J && a.n_groups == 1 && !masked) ? (double)a.J[p[k]] : 0.0;
     }
     const double two_pi = 6.283185307179586476925;
     auto zero_cpart = [&](int64_t it) {
@@ -393,6 +416,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         }
     };
     for (int64_t it = it_lo; it < it_hi; ++it) {
+        // with a mask, only the flagged (tile, step) pairs; every wave reads a flag before
+        // thread 0 changes it below (after the barriers of wg_extent), and the workgroups of
+        // the tile's other parts change only their own bits
+        if (masked) {
+            it = next_flagged(a.mask, a.n_tiles, tile, my_bits, it, it_hi);
+            if (it >= it_hi) break;
+        }
         // empty asm statements that the compiler must assume rewrite p and the thread index:
         // the addresses derived from them are then formed again per item instead of being
         // hoisted out of the item loop, where they held registers through the phase loops
@@ -438,8 +468,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
             }
         }
         wg_extent(dlo, dhi, tlo, thi, s_i, s_f);
+        uint8_t* const dflag = deferred + ((int64_t)e * a.kc + kk) * a.n_tiles + tile;
         if (dhi < dlo) {                               // no grid cell in this tile: nothing to add
-            if (tid == 0 && seg == 0) deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = 0;
+            if (tid == 0 && seg == 0) {
+                if (masked)
+                    clear_deferral_bits(dflag, my_bits);
+                else
+                    *dflag = 0;
+            }
             zero_cpart(it);
             continue;
         }
@@ -463,7 +499,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
         constexpr int kTapLo = kMode == GEOLOC_DELAY_SINC ? kSincLo : 0;
         const bool fact = Q > 0 && spread + kTaps <= kFH;
         if (tid == 0 && seg == 0) {
-            deferred[((int64_t)e * a.kc + kk) * a.n_tiles + tile] = fact ? 0 : 1;
+            if (!masked)
+                *dflag = fact ? 0 : (uint8_t)my_bits;
+            else if (fact)
+                clear_deferral_bits(dflag, my_bits);
             if (!fact) *a.defer_flag = a.defer_seq;
         }
         if (!fact) {                                   // uniform: the per-point kernel takes it
@@ -524,10 +563,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
 #pragma unroll
     for (int k = 0; k < kPPT; ++k) {
         if (!valid[k]) continue;
-        if (a.n_groups == 1)
-            a.J[p[k]] = (float)jacc[k];
-        else
-            a.partial[(int64_t)group * a.P + p[k]] = (float)jacc[k];
+        float* dst = a.n_groups == 1 ? a.J + p[k] : a.partial + (int64_t)group * a.P + p[k];
+        // a masked pass adds onto what the first pass wrote (nothing to write where it added 0)
+        if (masked) {
+            if (jacc[k] != 0.0) *dst = (float)((double)*dst + jacc[k]);
+        } else {
+            *dst = (float)jacc[k];
+        }
     }
 }
 
@@ -561,7 +603,7 @@ hipError_t launch_direct_seg_reduce(const DirectArgs& a, hipStream_t s) {
 
 template <int kQMax, int kPPT, int kSub>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
-    dim3 grid((unsigned)(a.n_tiles * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
+    dim3 grid((unsigned)(a.n_tiles * a.parts * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
     // four cells per thread take three waves per SIMD too: the spills of that register budget
     // (up to 216 bytes per lane) fall in the per-item set-up, none in the phase loops
     constexpr int kW = kQMax > 4 ? 2 : (kPPT == 4 ? 3 : (kSub == 4 ? 4 : 3));
@@ -589,11 +631,17 @@ static void launch_fact_sub(const DirectArgs& a, uint8_t* deferred, int32_t dela
         launch_fact_q<kQMax, kPPT, 1>(a, deferred, delay_mode, s);
 }
 
-hipError_t launch_direct_fact(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
+hipError_t launch_direct_fact(const DirectArgs& args, uint8_t* deferred, int32_t delay_mode, bool wide_doppler,
                               int32_t sub_blocks, hipStream_t s) {
-    const int lanes = tile_lanes(a.tiling);
-    if ((lanes != 256 && lanes != 512 && lanes != 1024) || (sub_blocks != 1 && sub_blocks != 4))
+    DirectArgs a = args;
+    if (a.parts < 1 || !a.mask) a.parts = 1;
+    const int all = tile_lanes(a.tiling);
+    const int lanes = all / a.parts;
+    if (lanes * a.parts != all || (lanes != 256 && lanes != 512 && lanes != 1024) ||
+        (sub_blocks != 1 && sub_blocks != 4))
         return hipErrorInvalidValue;
+    // a masked pass: 256-cell parts with 64-sample blocks (the only variant compiled for it)
+    if (a.mask && (lanes != 256 || sub_blocks != 1)) return hipErrorInvalidValue;
     // 1024-cell tiles: LINEAR and ROUND with at most four Taylor terms
     if (lanes == 1024 && (wide_doppler || delay_mode == GEOLOC_DELAY_SINC)) return hipErrorInvalidValue;
     if (lanes == 1024) {

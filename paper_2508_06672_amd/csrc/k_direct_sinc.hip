@@ -22,24 +22,31 @@ __global__ __launch_bounds__(256) void k_direct_sinc(DirectArgs a) {
     const int halves = tile_lanes(a.tiling) / 256;
     const int64_t sub = blockIdx.x % (a.n_tiles * halves);
     const int64_t tile = sub / halves;
-    const int lane = (int)(sub - tile * halves) * 256 + tid;
+    const int half = (int)(sub - tile * halves);
+    const int lane = half * 256 + tid;
     const int group = (int)(blockIdx.x / (a.n_tiles * halves));
     const int64_t n_items = (int64_t)a.n_pairs * a.kc;
     const int64_t it_lo = n_items * group / a.n_groups;
     const int64_t it_hi = n_items * (group + 1) / a.n_groups;
     bool valid;
     const int64_t p = tile_point(a.tiling, tile, lane, &valid);
+    // a wave without a grid cell has nothing to do (this kernel has no barriers)
+    if (__ballot(valid) == 0) return;
     double jacc = 0.0;
     if (valid && a.n_groups == 1 && a.load_J) jacc = (double)a.J[p];
     if (valid && a.n_groups > 1 && a.mask) jacc = (double)a.partial[(int64_t)group * a.P + p];
     const double centre = 0.5 * (double)(a.L - 1);
 
     for (int64_t it = it_lo; it < it_hi; ++it) {
+        // with a mask, only this 256-cell part of the (tile, step) pairs the factored kernel
+        // left over (the search needs every lane of the wave: the lanes without a cell run
+        // the body on point 0 and never store their sum)
+        if (a.mask) {
+            it = next_flagged(a.mask, a.n_tiles, tile, 1u << half, it, it_hi);
+            if (it >= it_hi) break;
+        }
         const int e = (int)(it / a.kc);
         const int kk = (int)(it - (int64_t)e * a.kc);
-        // with a mask, only the (tile, step) pairs the factored kernel left over
-        if (a.mask && !a.mask[((int64_t)e * a.kc + kk) * a.n_tiles + tile]) continue;
-        if (!valid) continue;
         const int2 pr = a.pairs[e];
         const float2* __restrict__ yi = a.cap + (int64_t)pr.x * a.N;
         const float2* __restrict__ yj = a.cap + (int64_t)pr.y * a.N;

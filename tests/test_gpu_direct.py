@@ -300,8 +300,8 @@ def test_step_segments(torch, G, delay, accum, spacing):
                                                         (16, 64, 0, 0, 8000.0, 0), (8, 64, -318, 0, 500.0, 2)])
 def test_fixed_tilings_match_oracle(torch, G, w, h, shear, tr, spacing, delay):
     """Tilings the plan would not pick, fixed through geoloc_set_tiling: 512- and 1024-cell
-    tiles on 8 km cells (most tile-steps deferred to the per-point kernel in 256-lane
-    parts), 1024-cell tiles (four cells per thread) in LINEAR and ROUND, steep and
+    tiles on 8 km cells (most tile-steps deferred to the second factored pass and the
+    per-point kernel in 256-cell parts), 1024-cell tiles (four cells per thread) in LINEAR and ROUND, steep and
     fractional shears, both orientations, SINC on 256- and 512-cell tiles; all match the oracle.
     Returning to the per-map choice works, and bad tilings are rejected."""
     wl = configs.MAP_1E6.with_(n_rows=45, n_cols=52, spacing_m=spacing, n_samples=30_000)
@@ -360,6 +360,36 @@ def test_taylor_blocks_match_oracle(torch, G, block, delay, spacing, step):
         J2 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
         assert plan.info()["taylor_block"] in (64, 256)
         assert err_J(J2, Jo) <= DIRECT_TOL
+
+
+@pytest.mark.parametrize("w,h,delay,step", [(16, 16, 0, 10_000), (16, 32, 1, 7_000), (16, 64, 0, 10_000),
+                                          (32, 32, 1, 10_000), (8, 32, 2, 7_000), (16, 64, 0, 41_000)])
+def test_deferred_pairs_second_factored_pass(torch, G, w, h, delay, step):
+    """8 km cells with 256-sample Taylor blocks defer many (tile, step) pairs; a second
+    factored pass takes them again in 256-cell parts of the tile with 64-sample blocks and
+    the per-point kernel adds the parts it defers again. With 256- to 1024-cell tiles, item
+    groups or (41,000-sample steps) segments, the map matches the oracle and the map made
+    with 64-sample blocks throughout."""
+    wl = configs.MAP_1E6.with_(n_rows=47, n_cols=61, spacing_m=8000.0, n_samples=3 * step, step_len=step)
+    scn = sim.make_scenario(wl, 700 + w + h + delay)
+    log(f"second pass: tile {w}x{h} delay {delay} step {step}")
+    Jo = oracle.map_scenario(scn, delay_mode=delay)
+    caps = torch.from_numpy(scn.captures).cuda()
+    with G.Plan.for_scenario(scn, delay_mode=delay) as plan:
+        plan.set_tiling(w, h, 0, 0)
+        plan.set_taylor_block(256)
+        plan.set_timing(True)
+        J256 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+        info = plan.info()
+        plan.set_taylor_block(64)
+        J64 = plan.map(caps, scn.states).cpu().numpy().astype(np.float64)
+    log(f"  segments {info['step_segments']}: err_J {err_J(J256, Jo):.3g} "
+        f"(64-sample blocks {err_J(J64, Jo):.3g}), deferred passes {info['interp_ms']:.3f} ms")
+    assert info["taylor_block"] == 256
+    assert err_J(J256, Jo) <= DIRECT_TOL
+    assert err_J(J64, Jo) <= DIRECT_TOL
+    assert err_J(J256, J64) <= DIRECT_TOL
+    check_argmax(J256, Jo, DIRECT_TOL)
 
 
 @pytest.mark.parametrize("seed,n_cases,shapes", [
