@@ -318,11 +318,11 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
 // are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
 // Tiles of 1024 cells (four per thread, LINEAR and ROUND, at most four Taylor terms) share
-// each moment among twice as many cells, at three waves per SIMD like the 256- and 512-cell
-// LINEAR kernels; where those run four (ROUND, and LINEAR items of at least kLongItem
-// samples, with 256-sample blocks) the 1024-cell work is counted 1.15 times. On the 1e6-point
-// map the LINEAR map took 10.3 ms on 16 x 64 tiles against 13.7 ms on 8 x 64 (the model's
-// ratio 0.81), ROUND 9.6 ms on 8 x 128 against 11.0 ms (model 0.76). A
+// each moment among twice as many cells; LINEAR runs them at three waves per SIMD like its
+// 256- and 512-cell kernels, and where those run four (items of at least kLongItem samples,
+// with 256-sample blocks) the 1024-cell work is counted 1.15 times. ROUND runs every
+// kernel with 256-sample blocks at four waves. On the 1e6-point map the LINEAR map took
+// 10.3 ms on 16 x 64 tiles against 13.7 ms on 8 x 64 (the model's ratio 0.81). A
 // fixed tiling (geoloc_set_tiling) keeps its shape and never takes the wide variant; only its
 // block length is chosen.
 void choose_tiling(geoloc_plan_t p, const double* states) {
@@ -446,7 +446,7 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
         double occupancy = 1.0;
         if (lanes == 1024) {
             const int64_t item = p->n_segs > 1 ? p->seg_len : p->L;
-            const bool four = sub == 4 && (p->delay_mode == GEOLOC_DELAY_ROUND || item >= kLongItem);
+            const bool four = sub == 4 && p->delay_mode != GEOLOC_DELAY_ROUND && item >= kLongItem;
             occupancy = four ? 1.15 : 1.0;
         }
         return total * (double)(t.tiles_x * t.tiles_y * lanes) / (double)p->P * fill(t) * occupancy;
