@@ -81,8 +81,8 @@ def tile_index(rows: int, cols: int, w: int, h: int, shear: int, transpose: int)
     return np.where(valid, rr * cols + cc, -1)
 
 
-def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int = 10):
-    """Algorithmic FP32 operations of one map in the tile-factored form, from the map's own
+def factored_work(torch, plan, wl, states, chunk: int = 10):
+    """Algorithmic FP32 operations of one LINEAR map in the tile-factored form, from the map's own
     geometry, with each tile (of the shape the plan chose for the map) and step classified
     as the kernel does (lag spread H = max d0 - min d0 + 2, Taylor order Q from the tile's
     Doppler spread over the plan's Taylor block of B = 64 or 256 samples, deferred when
@@ -91,8 +91,8 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     for B = 256, per lag and sub-block the shift to the long block's centre (Q (Q - 1) / 2
     complex multiply-adds by a real weight, 4 flops each) and per lag and long block the sum
     of its four sub-blocks (3 Q complex additions); per point and Taylor block 4 flops per
-    Taylor term and lag read (two lags for LINEAR, whose interpolation weights are folded
-    into the Taylor coefficients; one for ROUND) and 6 for the block weight (one Horner step,
+    Taylor term and lag read (two lags, whose interpolation weights are folded into the
+    Taylor coefficients) and 6 for the block weight (one Horner step,
     a complex product by a unit phasor). Returns (flops, factored units, deferred
     tile-steps, all tile-steps)."""
     import numpy as np
@@ -116,7 +116,7 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
     for k0 in range(0, wl.n_steps, chunk):
         n = min(chunk, wl.n_steps - k0)
         D, nu = plan.geometry(states, 0, k0, n)
-        d0 = torch.round(D) if delay_round else torch.floor(D)
+        d0 = torch.floor(D)
         th = (2 * np.pi * (nu / wl.fs_hz)).float()
 
         def tiles(x, fill):
@@ -134,7 +134,7 @@ def factored_work(torch, plan, wl, states, delay_round: bool = False, chunk: int
         ok = (terms <= FTOL) & (xr < 1).unsqueeze(-1)
         Q = torch.where(ok.any(-1), ok.float().argmax(-1) + 1, torch.zeros_like(xr, dtype=torch.int64)).double()
         fac = (Q > 0) & (H <= FH) & (nval > 0)     # tiles with no grid cell do no work
-        per_point = nblk * ((4 if delay_round else 8) * Q + 6)
+        per_point = nblk * (8 * Q + 6)
         f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
         if sub > 1:
             f = f + H * nsub * 2 * Q * (Q - 1) + H * nblk * 2 * Q * (sub - 1)
