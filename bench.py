@@ -87,8 +87,11 @@ def factored_work(torch, plan, wl, states, chunk: int = 10):
     as the kernel does (lag spread H = max d0 - min d0 + 2, Taylor order Q from the tile's
     Doppler spread over the plan's Taylor block of B = 64 or 256 samples, deferred when
     H > 128 or no Q <= 4 bounds the remainder). Per factored tile and step: rotation of the
-    reference samples 6 L; lag moments of the 64-sample sub-blocks H L (6 + 2 + 4 (Q - 1));
-    for B = 256, per lag and sub-block the shift to the long block's centre (Q (Q - 1) / 2
+    reference samples 6 L; lag moments of the 64-sample sub-blocks from running sums,
+    H L (8 + 2 (Q - 1)) (the complex product accumulated into the first level by four FMAs,
+    one complex addition per higher level), and per lag and sub-block their basis change to
+    powers of the offset from the sub-block centre, 2 (Q - 1) (Q + 1); for B = 256, per lag
+    and sub-block the shift to the long block's centre (Q (Q - 1) / 2
     complex multiply-adds by a real weight, 4 flops each) and per lag and long block the sum
     of its four sub-blocks (3 Q complex additions); per point and Taylor block 4 flops per
     Taylor term and lag read (two lags, whose interpolation weights are folded into the
@@ -135,7 +138,7 @@ def factored_work(torch, plan, wl, states, chunk: int = 10):
         Q = torch.where(ok.any(-1), ok.float().argmax(-1) + 1, torch.zeros_like(xr, dtype=torch.int64)).double()
         fac = (Q > 0) & (H <= FH) & (nval > 0)     # tiles with no grid cell do no work
         per_point = nblk * (8 * Q + 6)
-        f = 6 * L + H * L * (4 * Q + 4) + nval * per_point
+        f = 6 * L + H * L * (2 * Q + 6) + H * nsub * 2 * (Q - 1) * (Q + 1) + nval * per_point
         if sub > 1:
             f = f + H * nsub * 2 * Q * (Q - 1) + H * nblk * 2 * Q * (sub - 1)
         flops += float(torch.where(fac, f, torch.zeros_like(f)).sum())

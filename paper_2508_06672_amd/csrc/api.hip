@@ -306,7 +306,7 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // centre (middle step) of every pair, the candidate (shape of 256, 512 or 1024 cells, shear of
 // whole columns per row or along a pair's lines of equal delay) with the least predicted
 // VALU work per correlation summed over the pairs, counting the lanes its tiles leave
-// outside the grid. The lag moments cost about (8 + 4Q) instructions per lag pair and
+// outside the grid. The lag moments cost about (4 + 4Q) instructions per lag pair and
 // sample, shared by the tile's cells (waves without a (block, lag pair) item skip them),
 // and the per-point combination about (4Q + 6) / B per Taylor block of B samples (LINEAR;
 // fewer for ROUND, more for SINC), or the time of its LDS reads where that is longer; a tile that the factored kernel would defer costs about
@@ -435,9 +435,10 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
                 const int Hg = (int)std::ceil(H / 2.0);
                 const int NB = std::min(32 / sub, 256 / (sub * Hg));     // Taylor blocks per round
                 const double waves = std::ceil(NB * sub * Hg / 64.0);   // waves busy with moments
-                // per lane and sub-block: the shift to the long block's centre and the quad sums
-                const double extra = sub > 1 ? 2.0 * Q * (Q - 1) + 8.0 * Q : 0.0;
-                c = ((8.0 + 4.0 * Q + extra / 64.0) * waves * 64.0 / (NB * sub * lanes) + combine(Q) / (64.0 * sub)) *
+                // per lane and sub-block: the moments' basis change, and for long blocks the shift
+                // to the long block's centre and the quad sums
+                const double extra = 2.0 * (Q - 1) * (Q + 2) + (sub > 1 ? 2.0 * Q * (Q - 1) + 8.0 * Q : 0.0);
+                c = ((4.0 + 4.0 * Q + extra / 64.0) * waves * 64.0 / (NB * sub * lanes) + combine(Q) / (64.0 * sub)) *
                     (Q > 4 ? 1.5 : 1.0);
                 *q_need = std::max(*q_need, Q);
             }

@@ -129,97 +129,74 @@ struct MomentBasisTable {
 };
 
 // Moments of one block for the lag pair (l, l + 1) of this lane, y = s_y + block start + l:
-// G0[q] = sum_r r'^q v[r] conj(y[r]), G1[q] = sum_r r'^q v[r] conj(y[r + 1]), r' = r - 31.5.
-// kRunning = false: z_r = v[r] conj(y[r + d]) is formed and added with each power of r'
-// (4 + 2Q instructions per lag and sample). kRunning = true: the iterated running sums above,
-// the complex product folded into S_0 by two FMAs per component and one addition per
-// component and higher level (2 + 2Q per lag and sample), then the basis change. The
-// running sums need an empty volatile asm statement per sample that holds each level at
-// its sample (without it the compiler put the higher levels' additions off and kept every
-// sample's lower-level sums live: hundreds of bytes of spills per lane); it also keeps the
-// compiler from moving LDS reads ahead across samples, which costs the three-wave kernels
-// more than the instructions save, so only the four-wave ROUND and SINC variants take it.
-template <int Q, bool kRunning>
+// G0[q] = sum_r r'^q v[r] conj(y[r]), G1[q] = sum_r r'^q v[r] conj(y[r + 1]), r' = r - 31.5,
+// from the iterated running sums above: the complex product folds into S_0 (two FMAs per
+// component) and each higher level costs one addition per component, 2 + 2Q instructions
+// per lag and sample against 4 + 2Q for forming z_r = v[r] conj(y[r + d]) and adding it
+// with each power of r', and fewer registers; the basis change follows at the block's end.
+// An empty volatile asm statement per sample holds every level at its sample: without it
+// the compiler put the higher levels' additions off to the end of the block and kept every
+// sample's lower-level sums live (hundreds of bytes of spills per lane). Such statements
+// also keep the compiler from moving the LDS reads ahead across samples, so the loop reads
+// them kPF samples ahead itself.
+template <int Q>
 __device__ inline void block_moments2(const float2* __restrict__ v, const float2* __restrict__ y, float2 (&G0)[Q],
                                       float2 (&G1)[Q]) {
-    if constexpr (kRunning) {
-        float2 S0[Q], S1[Q];
+    constexpr int kPF = 2;
+    float2 S0[Q], S1[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            S0[q] = make_float2(0.f, 0.f);
-            S1[q] = make_float2(0.f, 0.f);
+    for (int q = 0; q < Q; ++q) {
+        S0[q] = make_float2(0.f, 0.f);
+        S1[q] = make_float2(0.f, 0.f);
+    }
+    float2 xb[kPF], yb[kPF];
+#pragma unroll
+    for (int r = 0; r < kPF; ++r) {
+        xb[r] = v[r];
+        yb[r] = y[r + 1];
+    }
+    float2 t0 = y[0];
+#pragma unroll
+    for (int r = 0; r < kFB; ++r) {
+        const float2 x = xb[r % kPF];
+        const float2 t1 = yb[r % kPF];
+        if (r + kPF < kFB) {
+            xb[r % kPF] = v[r + kPF];
+            yb[r % kPF] = y[r + kPF + 1];
         }
-        float2 t0 = y[0];
+        // S_0 += x conj(t)
+        S0[0].x = fmaf(x.y, t0.y, fmaf(x.x, t0.x, S0[0].x));
+        S0[0].y = fmaf(-x.x, t0.y, fmaf(x.y, t0.x, S0[0].y));
+        S1[0].x = fmaf(x.y, t1.y, fmaf(x.x, t1.x, S1[0].x));
+        S1[0].y = fmaf(-x.x, t1.y, fmaf(x.y, t1.x, S1[0].y));
 #pragma unroll
-        for (int r = 0; r < kFB; ++r) {
-            const float2 x = v[r];
-            const float2 t1 = y[r + 1];
-            // S_0 += x conj(t)
-            S0[0].x = fmaf(x.y, t0.y, fmaf(x.x, t0.x, S0[0].x));
-            S0[0].y = fmaf(-x.x, t0.y, fmaf(x.y, t0.x, S0[0].y));
-            S1[0].x = fmaf(x.y, t1.y, fmaf(x.x, t1.x, S1[0].x));
-            S1[0].y = fmaf(-x.x, t1.y, fmaf(x.y, t1.x, S1[0].y));
-#pragma unroll
-            for (int k = 1; k < Q; ++k) {
-                S0[k].x += S0[k - 1].x;
-                S0[k].y += S0[k - 1].y;
-                S1[k].x += S1[k - 1].x;
-                S1[k].y += S1[k - 1].y;
-            }
-            t0 = t1;
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-                asm volatile("" : "+v"(S0[k].x), "+v"(S0[k].y), "+v"(S1[k].x), "+v"(S1[k].y));
+        for (int k = 1; k < Q; ++k) {
+            S0[k].x += S0[k - 1].x;
+            S0[k].y += S0[k - 1].y;
+            S1[k].x += S1[k - 1].x;
+            S1[k].y += S1[k - 1].y;
         }
-        constexpr const MomentBasis<Q>& B = MomentBasisTable<Q>::m;
+        t0 = t1;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            float2 g0 = S0[q], g1 = S1[q];   // A[q][q] = (-1)^q q!
-            g0.x *= B.a[q][q];
-            g0.y *= B.a[q][q];
-            g1.x *= B.a[q][q];
-            g1.y *= B.a[q][q];
+        for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(S0[k].x), "+v"(S0[k].y), "+v"(S1[k].x), "+v"(S1[k].y));
+    }
+    constexpr const MomentBasis<Q>& B = MomentBasisTable<Q>::m;
 #pragma unroll
-            for (int k = 0; k < q; ++k) {
-                g0.x = fmaf(B.a[q][k], S0[k].x, g0.x);
-                g0.y = fmaf(B.a[q][k], S0[k].y, g0.y);
-                g1.x = fmaf(B.a[q][k], S1[k].x, g1.x);
-                g1.y = fmaf(B.a[q][k], S1[k].y, g1.y);
-            }
-            G0[q] = g0;
-            G1[q] = g1;
+    for (int q = 0; q < Q; ++q) {
+        float2 g0 = S0[q], g1 = S1[q];   // A[q][q] = (-1)^q q!
+        g0.x *= B.a[q][q];
+        g0.y *= B.a[q][q];
+        g1.x *= B.a[q][q];
+        g1.y *= B.a[q][q];
+#pragma unroll
+        for (int k = 0; k < q; ++k) {
+            g0.x = fmaf(B.a[q][k], S0[k].x, g0.x);
+            g0.y = fmaf(B.a[q][k], S0[k].y, g0.y);
+            g1.x = fmaf(B.a[q][k], S1[k].x, g1.x);
+            g1.y = fmaf(B.a[q][k], S1[k].y, g1.y);
         }
-    } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            G0[q] = make_float2(0.f, 0.f);
-            G1[q] = make_float2(0.f, 0.f);
-        }
-        float2 t0 = y[0];
-#pragma unroll
-        for (int r = 0; r < kFB; ++r) {
-            const float2 x = v[r];
-            const float2 t1 = y[r + 1];
-            const float z0r = fmaf(x.x, t0.x, x.y * t0.y);     // x * conj(t0)
-            const float z0i = fmaf(x.y, t0.x, -(x.x * t0.y));
-            const float z1r = fmaf(x.x, t1.x, x.y * t1.y);     // x * conj(t1)
-            const float z1i = fmaf(x.y, t1.x, -(x.x * t1.y));
-            G0[0].x += z0r;
-            G0[0].y += z0i;
-            G1[0].x += z1r;
-            G1[0].y += z1i;
-            const float rr = (float)r - 0.5f * (float)(kFB - 1);
-            float w = 1.f;
-#pragma unroll
-            for (int q = 1; q < Q; ++q) {
-                w *= rr;                                    // a compile-time constant per (r, q)
-                G0[q].x = fmaf(w, z0r, G0[q].x);
-                G0[q].y = fmaf(w, z0i, G0[q].y);
-                G1[q].x = fmaf(w, z1r, G1[q].x);
-                G1[q].y = fmaf(w, z1i, G1[q].y);
-            }
-            t0 = t1;
-        }
+        G0[q] = g0;
+        G1[q] = g1;
     }
 }
 
@@ -289,7 +266,7 @@ struct FactPoint {
 typedef float lds_vec2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) const lds_vec2 lds_cv2;
 
-template <int kMode, int Q, int kPPT, int kSub, bool kRunning>
+template <int kMode, int Q, int kPPT, int kSub>
 __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, const float2* __restrict__ yj,
                           const FactStep& st, const FactPoint (&pt)[kPPT], float2* s_y, float2* s_v, float2* s_G,
                           const float2* s_rot, float (&cr)[kPPT], float (&ci)[kPPT], int tid) {
@@ -355,7 +332,7 @@ __device__ void fact_step(const DirectArgs& a, const float2* __restrict__ yi, co
             if (st.my_b < st.NB && b < nblk) {      // uniform over the lanes of a long block
                 float2 G[2][Q];
                 const int sb = b * kSub + st.my_s;
-                block_moments2<Q, kRunning>(s_v + sb * kFVS, s_y + sb * kFB + st.my_l, G[0], G[1]);
+                block_moments2<Q>(s_v + sb * kFVS, s_y + sb * kFB + st.my_l, G[0], G[1]);
                 if constexpr (kSub > 1) {
                     static_assert(kSub == 4, "sub-block sums are taken over a quad");
                     const float o = ((float)st.my_s - 0.5f * (float)(kSub - 1)) * (float)kFB;
@@ -466,8 +443,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
     __shared__ float s_f[2][4];
 
     const int tid = threadIdx.x;
-    // phase-1 moments from running sums in the four-wave ROUND and SINC variants
-    constexpr bool kRunning = kMode != GEOLOC_DELAY_LINEAR && kWaves == 4;
     // a pass over the tile-steps that an earlier factored launch deferred (a.mask set; only
     // the variant with one cell per thread and 64-sample blocks takes one): it has nothing to
     // do unless that launch flagged some (uniform over the workgroup)
@@ -650,12 +625,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) v
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) cr[k] = ci[k] = 0.f;
         switch (Q) {
-            case 1: fact_step<kMode, 1, kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
-            case 2: fact_step<kMode, 2, kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
-            case 3: fact_step<kMode, 3, kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
-            case 4: fact_step<kMode, 4, kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
-            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4), kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
-            default: fact_step<kMode, kQMax, kPPT, kSub, kRunning>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            case 1: fact_step<kMode, 1, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            case 2: fact_step<kMode, 2, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            case 3: fact_step<kMode, 3, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            case 4: fact_step<kMode, 4, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            case 5: fact_step<kMode, (kQMax > 4 ? 5 : 4), kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
+            default: fact_step<kMode, kQMax, kPPT, kSub>(a, yi, yj, st, pt, s_y, s_v, s_G, s_rot, cr, ci, tidl); break;
         }
 #pragma unroll
         for (int k = 0; k < kPPT; ++k) {
@@ -713,8 +688,8 @@ template <int kQMax, int kPPT, int kSub>
 static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_mode, hipStream_t s) {
     dim3 grid((unsigned)(a.n_tiles * a.parts * a.n_groups * (a.n_segs > 1 ? a.n_segs : 1))), block(256);
     // four cells per thread take three waves per SIMD too: the spills of that register budget
-    // (40 bytes per lane for LINEAR) fall in the per-item set-up, none in the phase loops.
-    // ROUND, whose running-sum moments need fewer registers, takes four with 256-sample blocks.
+    // fall in the per-item set-up, none in the phase loops. ROUND, with fewer per-cell
+    // registers, takes four with 256-sample blocks.
     constexpr int kW = kQMax > 4 ? 2 : (kPPT == 4 ? 3 : (kSub == 4 ? 4 : 3));
     constexpr int kWRound = (kQMax <= 4 && kPPT == 4 && kSub == 4) ? 4 : kW;
     if (delay_mode == GEOLOC_DELAY_ROUND) {
