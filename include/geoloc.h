@@ -203,8 +203,7 @@ int geoloc_set_points_from_tiles(geoloc_plan_t plan, const double* lat_dev, cons
 
 /* Fix the tiling of the tile-factored kernel for the maps that follow (RECT grids, method
  * GEOLOC_DIRECT_FP32), instead of the per-map choice from the geometry: tiles of tile_h rows
- * of tile_w cells (tile_w x tile_h = 256, or 512 or 1024 for two or four cells per thread;
- * SINC 256 or 512),
+ * of tile_w cells (tile_w x tile_h = 256, or 512 or 1024 for two or four cells per thread),
  * row i starting floor(shear * i / 256) columns further along, |shear| <= 1024, rows and
  * columns swapped if transpose. tile_w = 0 returns to the per-map choice. The map is the
  * same function of the inputs whatever the tiling (to FP32 rounding); only its speed and

@@ -314,14 +314,16 @@ void host_delay_doppler(const geoloc_plan_s* p, int64_t r, int64_t c, const doub
 // block's centre and summed) cut the per-point share fourfold but need more Taylor terms
 // for the same Doppler spread; both block lengths are priced. A tiling whose launch has
 // fewer than 768 workgroups (three per CU) is charged for the idle share of the chip, and
-// SINC keeps to tiles of 256 or 512 cells at most 8 cells wide. Taylor orders 5 and 6 need the kernel's
+// SINC keeps to tiles at most 8 cells wide, or 16 x 64. Taylor orders 5 and 6 need the kernel's
 // wide-Doppler variant, whose larger LDS footprint costs a third of its occupancy: they
 // are counted 1.5 times, and the variant is launched when the chosen tiling needs them.
-// Tiles of 1024 cells (four per thread, LINEAR and ROUND, at most four Taylor terms) share
+// Tiles of 1024 cells (four per thread, at most four Taylor terms) share
 // each moment among twice as many cells; LINEAR runs them at three waves per SIMD like its
 // 256- and 512-cell kernels, and where those run four (items of at least kLongItem samples,
 // with 256-sample blocks) the 1024-cell work is counted 1.15 times. ROUND runs every
-// kernel with 256-sample blocks at four waves. On the 1e6-point map the LINEAR map took
+// kernel with 256-sample blocks at four waves. SINC runs its 16 x 64 tiles at three
+// against four for 512 cells, uncharged: they measured faster (above). On the 1e6-point
+// map the LINEAR map took
 // 10.3 ms on 16 x 64 tiles against 13.7 ms on 8 x 64 (the model's ratio 0.81). A
 // fixed tiling (geoloc_set_tiling) keeps its shape and never takes the wide variant; only its
 // block length is chosen.
@@ -469,10 +471,13 @@ void choose_tiling(geoloc_plan_t p, const double* states) {
     if (p->tiling_fixed) return;
     for (const auto& shape : p->tile_shapes) {
         // the SINC combination is bound by per-point work, registers and LDS reads: tiles of
-        // 256 or 512 cells at most 8 cells wide (on the 1e6-point map 16-wide tiles ran 1.4x
-        // slower, each wave's cells reading twice as many distinct lags per block; 8 x 64 took
-        // 23.4 ms against 30.8 ms on 4 x 64)
-        if (p->delay_mode == GEOLOC_DELAY_SINC && (tile_lanes(shape) > 512 || shape.tile_w > 8)) continue;
+        // 256 or 512 cells at most 8 cells wide (on the 1e6-point map 16-wide tiles of two
+        // cells per thread ran 1.4x slower, each wave's cells reading twice as many distinct
+        // lags per block; 8 x 64 took 23.4 ms against 30.8 ms on 4 x 64), and of the 1024-cell
+        // shapes 16 x 64 (21.3 ms; 32 x 32 23.9 ms, 8 x 128 24.4 ms)
+        if (p->delay_mode == GEOLOC_DELAY_SINC &&
+            (tile_lanes(shape) == 1024 ? shape.tile_w != 16 : shape.tile_w > 8))
+            continue;
         // shears: whole columns per row, and the slope of each pair's lines of equal delay
         std::vector<int32_t> shears = {-2 * kShearOne, -kShearOne, 0, kShearOne, 2 * kShearOne};
         for (const auto& g : grads) {
@@ -1077,8 +1082,6 @@ int geoloc_set_tiling(geoloc_plan_t p, int32_t tile_w, int32_t tile_h, int32_t s
     const int64_t cells = (int64_t)tile_w * tile_h;
     if (tile_w < 1 || tile_h < 1 || (cells != 256 && cells != 512 && cells != 1024))
         return fail(GEOLOC_EINVAL, "tile must hold 256, 512 or 1024 cells (got %d x %d)", tile_w, tile_h);
-    if (cells > 512 && p->delay_mode == GEOLOC_DELAY_SINC)
-        return fail(GEOLOC_EINVAL, "SINC takes tiles of 256 or 512 cells");
     if (shear < -kMaxShear || shear > kMaxShear) return fail(GEOLOC_EINVAL, "|shear| must be <= %d", kMaxShear);
     if (transpose != 0 && transpose != 1) return fail(GEOLOC_EINVAL, "transpose must be 0 or 1");
     PointTiling t = p->base_tiling;

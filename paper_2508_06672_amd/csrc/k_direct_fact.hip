@@ -695,8 +695,7 @@ static void launch_fact_q(const DirectArgs& a, uint8_t* deferred, int32_t delay_
     if (delay_mode == GEOLOC_DELAY_ROUND) {
         hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_ROUND, kQMax, kPPT, kSub, kWRound>), grid, block, 0, s, a, deferred);
     } else if (delay_mode == GEOLOC_DELAY_SINC) {
-        if constexpr (kPPT < 4)
-            hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
+        hipLaunchKernelGGL((k_direct_fact<GEOLOC_DELAY_SINC, kQMax, kPPT, kSub, kW>), grid, block, 0, s, a, deferred);
     } else if constexpr (kW == 4) {
         const int64_t item = a.n_segs > 1 ? (int64_t)a.seg_len : (int64_t)a.L;
         if (item < kLongItem)
@@ -727,8 +726,8 @@ hipError_t launch_direct_fact(const DirectArgs& args, uint8_t* deferred, int32_t
         return hipErrorInvalidValue;
     // a masked pass: 256-cell parts with 64-sample blocks (the only variant compiled for it)
     if (a.mask && (lanes != 256 || sub_blocks != 1)) return hipErrorInvalidValue;
-    // 1024-cell tiles: LINEAR and ROUND with at most four Taylor terms
-    if (lanes == 1024 && (wide_doppler || delay_mode == GEOLOC_DELAY_SINC)) return hipErrorInvalidValue;
+    // 1024-cell tiles: at most four Taylor terms
+    if (lanes == 1024 && wide_doppler) return hipErrorInvalidValue;
     if (lanes == 1024) {
         launch_fact_sub<kFQ, 4>(a, deferred, delay_mode, sub_blocks, s);
     } else if (lanes == 512) {
